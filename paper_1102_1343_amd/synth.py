@@ -1,0 +1,277 @@
+"""Seeded synthetic inputs for the fire-mesh time step.
+
+This module builds inputs only: fuel-category maps, category parameter sets,
+terrain gradients, surface wind fields and ignition records.  It contains none
+of the method's arithmetic (no spread rate, no level set, no fuel burn), so the
+HIP path and the CPU oracle can both be fed from it.
+
+The recipes stand in for the paper's real-data cases (FireFlux, Meadow Creek,
+Sect. 10), whose data are not available: they keep the fire/atmosphere
+refinement ratio of 10 (Sect. 8.2), the 13 fuel categories (Sect. 2.1), a
+fire-cell size of a few metres and the 6.1 m wind (Sect. 6).
+
+Every generator takes an explicit ``numpy.random.Generator`` (PCG64) so that
+a (recipe, seed) pair fixes the arrays bit for bit.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Standard constants for fuel quantities the workload recipes do not draw
+# (Rothermel/Anderson values for the dead fine fuel class).
+FUEL_DEFAULTS = dict(
+    windrf=1.0,        # a: the 6.1 m wind is used as midflame wind
+    tf=0.0,            # <= 0: derive T_f from weight
+    weight=1000.0,
+    fgi=0.5,           # kg/m^2
+    fueldepthm=0.5,    # m
+    savr=8000.0,       # 1/m
+    fuelmce=0.30,      # moisture of extinction
+    fueldens=512.0,    # kg/m^3 (32 lb/ft^3)
+    st=0.0555,
+    se=0.010,
+    cmbcnst=18.608e6,  # J/kg (8000 BTU/lb)
+    fuelmc_g=0.08,
+    ros_mult=1.0,
+    ichap=0,
+)
+
+FUEL_FIELDS = tuple(FUEL_DEFAULTS.keys())
+IGN_FIELDS = ("ax", "ay", "bx", "by", "t_start", "radius", "ros", "vx", "vy", "t_end")
+
+
+def fuel(**kw) -> dict:
+    """A fuel category record with defaults for unspecified fields."""
+    f = dict(FUEL_DEFAULTS)
+    for k, v in kw.items():
+        if k not in f:
+            raise KeyError(f"unknown fuel field {k!r}")
+        f[k] = v
+    return f
+
+
+def ignition(ax, ay, bx=None, by=None, t_start=0.0, radius=0.0, ros=math.inf,
+             vx=0.0, vy=0.0, t_end=0.0) -> dict:
+    """A segment ignition a-b (a point when b is omitted), or a drip torch when
+    (vx, vy) is non-zero."""
+    return dict(ax=float(ax), ay=float(ay),
+                bx=float(ax if bx is None else bx), by=float(ay if by is None else by),
+                t_start=float(t_start), radius=float(radius), ros=float(ros),
+                vx=float(vx), vy=float(vy), t_end=float(t_end))
+
+
+@dataclass
+class Problem:
+    """Everything one fire run needs, in float64 host arrays."""
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    sr_x: int
+    sr_y: int
+    fuels: list
+    cat: np.ndarray            # uint8 [ny, nx]
+    dzdx: np.ndarray           # float64 [ny, nx]
+    dzdy: np.ndarray
+    ignitions: list
+    dt: float
+    steps: int
+    wind: list                 # list of (u, v) float64 [ny, nx] fields
+    wind_period: int = 0       # steps per wind field (0: one field for all)
+    params: dict = field(default_factory=dict)
+    name: str = ""
+
+    def wind_at(self, step: int):
+        if self.wind_period <= 0 or len(self.wind) == 1:
+            return self.wind[0]
+        return self.wind[(step // self.wind_period) % len(self.wind)]
+
+    def cast(self, dtype) -> "Problem":
+        """Round every floating array to ``dtype`` and back to float64, so that a
+        float32 run and the float64 oracle see bit-identical input values."""
+        dt = np.dtype(dtype)
+        r = lambda a: np.ascontiguousarray(a.astype(dt).astype(np.float64))
+        return Problem(self.nx, self.ny, self.dx, self.dy, self.sr_x, self.sr_y,
+                       [dict(f) for f in self.fuels], self.cat.copy(), r(self.dzdx),
+                       r(self.dzdy), [dict(g) for g in self.ignitions], self.dt, self.steps,
+                       [(r(u), r(v)) for (u, v) in self.wind], self.wind_period,
+                       dict(self.params), self.name)
+
+
+# --------------------------------------------------------------------------
+# field generators
+# --------------------------------------------------------------------------
+
+def voronoi_categories(rng, nx, ny, nsites=256, ncat=13) -> np.ndarray:
+    """Fuel-category map made of Voronoi patches: ``nsites`` sites uniform in
+    the domain, each with a category uniform in 0..ncat-1; a cell takes the
+    category of its nearest site (cell-index metric)."""
+    from scipy.spatial import cKDTree
+
+    sx = rng.uniform(0.0, nx, nsites)
+    sy = rng.uniform(0.0, ny, nsites)
+    scat = rng.integers(0, ncat, nsites).astype(np.uint8)
+    tree = cKDTree(np.stack([sx, sy], axis=1))
+    out = np.empty((ny, nx), dtype=np.uint8)
+    xs = np.arange(nx) + 0.5
+    rows = max(1, (1 << 22) // max(nx, 1))
+    for j0 in range(0, ny, rows):
+        j1 = min(ny, j0 + rows)
+        yy, xx = np.meshgrid(np.arange(j0, j1) + 0.5, xs, indexing="ij")
+        _, idx = tree.query(np.stack([xx.ravel(), yy.ravel()], axis=1), workers=-1)
+        out[j0:j1] = scat[idx].reshape(j1 - j0, nx)
+    return out
+
+
+def hills_gradient(rng, nx, ny, dx, dy, nhills=8, max_slope=0.30):
+    """Analytic gradient of a sum of Gaussian hills z = sum_h A_h exp(-r^2/(2 s_h^2)).
+
+    Centres uniform in the domain, widths s_h uniform in [0.04, 0.15] L, peak
+    slopes g_h uniform in [0.05, 0.30] with A_h = g_h s_h e^(1/2) (the peak
+    slope of one hill).  The summed gradient is rescaled so its largest norm
+    is at most ``max_slope``.  Each hill is separable, so the fields are
+    built as rank-``nhills`` products.
+    """
+    L = max(nx * dx, ny * dy)
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    cx = rng.uniform(0, nx * dx, nhills)
+    cy = rng.uniform(0, ny * dy, nhills)
+    s = rng.uniform(0.04, 0.15, nhills) * L
+    g = rng.uniform(0.05, 0.30, nhills)
+    A = g * s * math.exp(0.5)
+    ex = np.exp(-((x[None, :] - cx[:, None]) ** 2) / (2 * s[:, None] ** 2))      # [h, nx]
+    ey = np.exp(-((y[None, :] - cy[:, None]) ** 2) / (2 * s[:, None] ** 2))      # [h, ny]
+    fx = -(A / s ** 2)[:, None] * (x[None, :] - cx[:, None]) * ex                  # d/dx factor
+    fy = -(A / s ** 2)[:, None] * (y[None, :] - cy[:, None]) * ey
+    dzdx = ey.T @ fx            # [ny, nx]
+    dzdy = fy.T @ ex
+    nrm = np.sqrt(dzdx ** 2 + dzdy ** 2).max()
+    if nrm > max_slope:
+        dzdx *= max_slope / nrm
+        dzdy *= max_slope / nrm
+    return np.ascontiguousarray(dzdx), np.ascontiguousarray(dzdy)
+
+
+def fourier_wind(rng, nx, ny, dx, dy, nmodes=16, mean_speed=4.0, max_speed=8.0,
+                 amp_scale=1.0, rotate_deg=0.0):
+    """Smooth surface wind: a mean wind (direction uniform, ``mean_speed``) plus
+    ``nmodes`` Fourier modes alpha_m cos(2 pi k_m.x / L + phi_m) with integer
+    wave vectors k_m in [-4,4]^2 minus 0 and independent amplitudes for u and
+    v; the whole field is then scaled so its largest speed is ``max_speed``.
+    ``amp_scale``/``rotate_deg`` perturb the result (ensemble members)."""
+    Lx, Ly = nx * dx, ny * dy
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    th = rng.uniform(0, 2 * math.pi)
+    k = np.zeros((nmodes, 2), dtype=np.int64)
+    for m in range(nmodes):
+        while True:
+            kk = rng.integers(-4, 5, 2)
+            if kk[0] != 0 or kk[1] != 0:
+                break
+        k[m] = kk
+    phi = rng.uniform(0, 2 * math.pi, nmodes)
+    au = rng.normal(0.0, 1.0, nmodes)
+    av = rng.normal(0.0, 1.0, nmodes)
+    ax_ = 2 * math.pi * k[:, 0][None, :] * x[:, None] / Lx + phi[None, :]   # [nx, m]
+    by_ = 2 * math.pi * k[:, 1][None, :] * y[:, None] / Ly                  # [ny, m]
+    X = np.concatenate([np.cos(ax_), np.sin(ax_)], axis=1)                 # [nx, 2m]
+    Yu = np.concatenate([au * np.cos(by_), -au * np.sin(by_)], axis=1)      # [ny, 2m]
+    Yv = np.concatenate([av * np.cos(by_), -av * np.sin(by_)], axis=1)
+    u = mean_speed * math.cos(th) + Yu @ X.T
+    v = mean_speed * math.sin(th) + Yv @ X.T
+    sp = np.sqrt(u ** 2 + v ** 2).max()
+    sc = max_speed / sp * amp_scale
+    c, s_ = math.cos(math.radians(rotate_deg)), math.sin(math.radians(rotate_deg))
+    ur = sc * (c * u - s_ * v)
+    vr = sc * (s_ * u + c * v)
+    return np.ascontiguousarray(ur), np.ascontiguousarray(vr)
+
+
+def random_fuels(rng, ncat=13) -> list:
+    """Category parameters drawn uniformly: load 0.1-3 kg/m^2, depth 0.1-2 m,
+    moisture 0.05-0.25, surface/volume 5000-12000 1/m; burn time T_f
+    log-uniform in [8, 1000] s; the rest at FUEL_DEFAULTS."""
+    out = []
+    for _ in range(ncat):
+        out.append(fuel(
+            fgi=float(rng.uniform(0.1, 3.0)),
+            fueldepthm=float(rng.uniform(0.1, 2.0)),
+            fuelmc_g=float(rng.uniform(0.05, 0.25)),
+            savr=float(rng.uniform(5000.0, 12000.0)),
+            tf=float(math.exp(rng.uniform(math.log(8.0), math.log(1000.0)))),
+        ))
+    return out
+
+
+def line_ignitions(rng, nx, ny, dx, dy, n=4, jitter_cells=0.0):
+    """``n`` line ignitions: start uniform in the central 50 % of the domain,
+    random direction, length uniform in [0.02, 0.06] L, t_g uniform in
+    [0, 10] s, r_g = 2 dx, S_g = 0.5 m/s."""
+    L = max(nx * dx, ny * dy)
+    out = []
+    for _ in range(n):
+        ax = rng.uniform(0.25, 0.75) * nx * dx
+        ay = rng.uniform(0.25, 0.75) * ny * dy
+        ang = rng.uniform(0, 2 * math.pi)
+        ln = rng.uniform(0.02, 0.06) * L
+        bx, by = ax + ln * math.cos(ang), ay + ln * math.sin(ang)
+        if jitter_cells:
+            ax += rng.uniform(-jitter_cells, jitter_cells) * dx
+            ay += rng.uniform(-jitter_cells, jitter_cells) * dy
+            bx += rng.uniform(-jitter_cells, jitter_cells) * dx
+            by += rng.uniform(-jitter_cells, jitter_cells) * dy
+        out.append(ignition(ax, ay, bx, by, t_start=float(rng.uniform(0, 10)),
+                            radius=2 * dx, ros=0.5))
+    return out
+
+
+# --------------------------------------------------------------------------
+# workload recipes
+# --------------------------------------------------------------------------
+
+SEED = 11021343
+
+
+def uniform_fire(n=128, dx=6.0, steps=200, dt=0.5, wind=(2.0, 0.0)) -> Problem:
+    """FP64 validation workload: n x n mesh, dx = 6 m, flat terrain, one fuel
+    (load 0.5 kg/m^2, depth 0.5 m, moisture 0.08, s/v 8000 1/m, T_f = 10 s),
+    constant 2 m/s wind along +x, one instantaneous circular ignition of radius
+    10 m at the centre at t = 0, dt = 0.5 s, atmosphere refinement 10."""
+    f = fuel(fgi=0.5, fueldepthm=0.5, fuelmc_g=0.08, savr=8000.0, tf=10.0)
+    z = np.zeros((n, n))
+    u = np.full((n, n), float(wind[0]))
+    v = np.full((n, n), float(wind[1]))
+    c = 0.5 * n * dx
+    ign = [ignition(c, c, t_start=0.0, radius=10.0, ros=math.inf)]
+    return Problem(n, n, dx, dx, 10, 10, [f], np.zeros((n, n), np.uint8), z, z.copy(), ign,
+                   dt, steps, [(u, v)], 0,
+                   dict(viscosity=0.4, viscosity_mode=0, ros_cap=math.inf,
+                        boundary_policy=0, guard_width=1), name=f"uniform{n}")
+
+
+def patchy_fire(n=2048, dx=6.0, steps=2000, dt=0.25, nwind=1, wind_period=0,
+                seed=SEED) -> Problem:
+    """FP32 production workload: n x n mesh, dx = 6 m, 13 fuel categories as
+    256 seeded Voronoi patches with random parameters, 8 Gaussian hills (slopes
+    up to 30 %), a 16-mode Fourier wind (0-8 m/s), 4 seeded line ignitions,
+    dt = 0.25 s, refinement 10, spread rate capped at 6 m/s.  With ``nwind`` > 1
+    several wind fields are drawn and cycled every ``wind_period`` steps
+    (time-varying coupling input)."""
+    rng = np.random.default_rng(seed)
+    fuels = random_fuels(rng)
+    cat = voronoi_categories(rng, n, n)
+    gzx, gzy = hills_gradient(rng, n, n, dx, dx)
+    ign = line_ignitions(rng, n, n, dx, dx)
+    winds = []
+    for w in range(max(1, nwind)):
+        wr = np.random.default_rng([seed, 1000 + w])
+        winds.append(fourier_wind(wr, n, n, dx, dx))
+    return Problem(n, n, dx, dx, 10, 10, fuels, cat, gzx, gzy, ign, dt, steps, winds,
+                   wind_period, dict(viscosity=0.4, viscosity_mode=0, ros_cap=6.0,
+                                     boundary_policy=1, guard_width=1),
+                   name=f"patchy{n}")

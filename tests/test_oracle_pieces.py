@@ -1,0 +1,264 @@
+"""Pins of the oracle's building blocks against what the paper and the
+mathematics fix: printed formulas evaluated by hand (tests/golden), textbook
+identities, exact special cases and brute force.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1102_1343_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    for ln in open(os.path.join(GOLD, name)):
+        ln = ln.split("#")[0].strip()
+        if ln:
+            out.append(ln.split())
+    return out
+
+
+# ------------------------------------------------------------- spread rate
+
+def test_chaparral_eq2_golden():
+    """Eq. (2) values (hand-evaluated) through the coefficient form Eq. (3)
+    and through the direct product-form routine."""
+    f = synth.fuel(ichap=1)
+    row = oracle.coef([f])[0]
+    for U, S in ((float(a), float(b)) for a, b in _rows("chaparral_eq2.txt")):
+        assert oracle.ros(row, U, 0.3) == pytest.approx(S, rel=1e-12, abs=1e-15)
+        assert oracle.ros_product(f, U, 0.3) == pytest.approx(S, rel=1e-12, abs=1e-15)
+
+
+def test_coefficient_form_equals_product_form():
+    """Eq. (3) (coefficients) and Eq. (1) (R0 (1 + phi_W + phi_S), Table 2
+    evaluated directly with the wind in ft/min) agree for random fuels, winds
+    and slopes, including clamped wind (< 0, > 30 m/s) and negative slope."""
+    rng = np.random.default_rng(7)
+    fuels = synth.random_fuels(rng, 20) + [synth.fuel(windrf=0.4), synth.fuel(windrf=0.36, savr=3500)]
+    tab = oracle.coef(fuels)
+    for k, f in enumerate(fuels):
+        for U in (-3.0, 0.0, 0.7, 2.0, 7.9, 29.0, 45.0):
+            for tp in (-0.4, 0.0, 0.05, 0.3, 0.9):
+                a = oracle.ros(tab[k], U, tp)
+                b = oracle.ros_product(f, U, tp)
+                assert a == pytest.approx(b, rel=1e-13), (k, U, tp)
+
+
+def test_rothermel_special_cases():
+    """Exact special cases of the Table 2 chain: at the moisture of extinction
+    eta_M vanishes (its cubic sums to zero) so R0 = 0; the reaction intensity
+    is linear in the heat content h, so R0, c and d scale with h while b and e
+    do not; no wind and no slope give S = R0."""
+    base = synth.fuel(fuelmc_g=0.05)
+    r_dry = oracle.coef([base])[0]
+    ext = oracle.coef([synth.fuel(fuelmc_g=0.30, fuelmce=0.30)])[0]
+    assert abs(ext[oracle.R0]) <= 1e-13 * r_dry[oracle.R0]
+    over = oracle.coef([synth.fuel(fuelmc_g=0.45, fuelmce=0.30)])[0]
+    assert abs(over[oracle.R0]) <= 1e-13 * r_dry[oracle.R0]
+    h2 = oracle.coef([synth.fuel(fuelmc_g=0.05, cmbcnst=2 * base["cmbcnst"])])[0]
+    for col in (oracle.R0, oracle.CC, oracle.D):
+        assert h2[col] == pytest.approx(2 * r_dry[col], rel=1e-14)
+    for col in (oracle.B, oracle.E, oracle.S0):
+        assert h2[col] == r_dry[col]
+    assert oracle.ros(r_dry, 0.0, 0.0) == pytest.approx(r_dry[oracle.R0], rel=1e-15)
+    assert oracle.ros(r_dry, -5.0, -0.2) == pytest.approx(r_dry[oracle.R0], rel=1e-15)
+
+
+def test_ros_monotone_and_clamped():
+    """S is non-decreasing in the normal wind and in the normal slope, flat in
+    the wind beyond the cap e = 30 m/s and for downhill slopes (Table 2
+    caption); the per-category multiplier and the upper cap act last."""
+    rng = np.random.default_rng(3)
+    tab = oracle.coef(synth.random_fuels(rng, 6))
+    for row in tab:
+        Us = np.linspace(-5, 40, 91)
+        S = np.array([oracle.ros(row, U, 0.1) for U in Us])
+        assert np.all(np.diff(S) >= 0)
+        assert np.all(S[Us >= 30] == S[-1]) and np.all(S[Us <= 0] == S[0])
+        ts = np.linspace(-1, 1, 41)
+        S2 = np.array([oracle.ros(row, 3.0, t) for t in ts])
+        assert np.all(np.diff(S2) >= 0) and np.all(S2[ts <= 0] == S2[0])
+        r2 = row.copy()
+        r2[oracle.M] = 2.5
+        assert oracle.ros(r2, 3.0, 0.2) == pytest.approx(2.5 * oracle.ros(row, 3.0, 0.2), rel=1e-15)
+        assert oracle.ros(row, 3.0, 0.2, ros_cap=1e-3) == 1e-3
+
+
+def test_flux_factors_and_burn_time_golden():
+    for fgi, h, mf, ch, cq in ((float(x) for x in r) for r in _rows("flux_factors.txt")):
+        row = oracle.coef([synth.fuel(fgi=fgi, cmbcnst=h, fuelmc_g=mf)])[0]
+        assert row[oracle.CH] == pytest.approx(ch, rel=1e-14)
+        assert row[oracle.CQ] == pytest.approx(cq, rel=1e-14)
+    # Eq. (4): with weight w, 40 % of the fuel is gone after 600 s at w = 1000
+    # and T_f is about w / 0.8514
+    for w in (7.0, 100.0, 1000.0, 850.0):
+        tf = oracle.coef([synth.fuel(tf=0.0, weight=w)])[0][oracle.TF]
+        assert tf == pytest.approx(w / 0.8514, rel=1e-4)
+    tf = oracle.coef([synth.fuel(tf=0.0, weight=1000.0)])[0][oracle.TF]
+    assert math.exp(-600.0 / tf) == pytest.approx(0.6, rel=1e-14)
+    assert oracle.coef([synth.fuel(tf=12.5)])[0][oracle.TF] == 12.5
+
+
+# ------------------------------------------------------------- level set pieces
+
+def test_ghost_extrapolation_golden():
+    rows = _rows("ghost_extrapolation.txt")
+    i = rows.index(["psi"])
+    j = rows.index(["ext"])
+    psi = np.array(rows[i + 1:j], dtype=float)
+    ext = np.array(rows[j + 1:], dtype=float)
+    assert np.array_equal(oracle.extrapolate(psi), ext)
+
+
+def test_extrapolation_linear_and_never_below():
+    """A field increasing towards the boundary is continued linearly; the
+    ghost is never below either node it comes from (Sect. 4.1)."""
+    y, x = np.mgrid[0:6, 0:7].astype(float)
+    lin = 1.5 * x + 0.25 * y + 3.0
+    e = oracle.extrapolate(lin)
+    assert np.allclose(e[1:-1, -1], 1.5 * 7 + 0.25 * np.arange(6) + 3.0, rtol=0, atol=1e-13)
+    assert np.allclose(e[-1, 1:-1], 1.5 * np.arange(7) + 0.25 * 6 + 3.0, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(0)
+    p = rng.normal(size=(5, 9))
+    e = oracle.extrapolate(p)
+    assert np.all(e[1:-1, 0] >= np.maximum(p[:, 0], p[:, 1]))
+    assert np.all(e[1:-1, -1] >= np.maximum(p[:, -1], p[:, -2]))
+    assert np.all(e[0, 1:-1] >= np.maximum(p[0], p[1]))
+    assert np.all(e[-1, 1:-1] >= np.maximum(p[-1], p[-2]))
+
+
+def test_godunov_cases_and_textbook_identity():
+    """The five cases of Eq. (13), and for every sign pattern the textbook
+    Godunov flux for S >= 0: selected^2 = max(max(D-,0)^2, min(D+,0)^2)."""
+    assert oracle.godunov(-1.0, -2.0) == -2.0      # both <= 0: right difference
+    assert oracle.godunov(1.0, 2.0) == 1.0         # both >= 0: left difference
+    assert oracle.godunov(-1.0, 2.0) == 0.0        # valley: zero
+    assert oracle.godunov(3.0, -1.0) == 3.0        # peak: larger magnitude
+    assert oracle.godunov(1.0, -3.0) == -3.0
+    assert oracle.godunov(0.0, 0.0) == 0.0
+    rng = np.random.default_rng(1)
+    for dm, dp in rng.normal(size=(2000, 2)):
+        g = oracle.godunov(dm, dp)
+        assert g * g == pytest.approx(max(max(dm, 0) ** 2, min(dp, 0) ** 2), rel=1e-15, abs=0)
+
+
+# ------------------------------------------------------------- fuel fraction
+
+def test_beta_exact_cases():
+    """Eq. (18) is exact when no part / all of the sub-cell burns, and for a
+    linear psi whose zero line is axis-aligned or runs along the diagonal."""
+    assert oracle.subcell_beta([1.0, 0.0, 2.0, 0.5]) == 0.0
+    assert oracle.subcell_beta([-1.0, 0.0, -2.0, -0.5]) == 1.0
+    assert oracle.subcell_beta([0.0, 0.0, 0.0, 0.0]) == 0.0
+    # corners ordered (0,0) (1,0) (0,1) (1,1); psi = x - s burns area s
+    for s in np.linspace(0.0, 1.0, 11):
+        psi = [0 - s, 1 - s, 0 - s, 1 - s]
+        assert oracle.subcell_beta(psi) == pytest.approx(s, abs=1e-15)
+        psi = [0 - s, 0 - s, 1 - s, 1 - s]          # psi = y - s
+        assert oracle.subcell_beta(psi) == pytest.approx(s, abs=1e-15)
+    # zero line on the diagonal x + y = 1: half the square burns
+    for g in (0.3, 1.0, 7.0):
+        psi = [g * (0 + 0 - 1), g * (1 + 0 - 1), g * (0 + 1 - 1), g * (1 + 1 - 1)]
+        assert oracle.subcell_beta(psi) == pytest.approx(0.5, abs=1e-15)
+
+
+def test_subcell_burned_sign_and_exponential():
+    """Whole sub-cell burning since t - s gives 1 - exp(-s/T_f) (Eq. 4); the
+    exponent has the sign of Eq. (4) so the burned fraction is positive."""
+    for s, T in ((1.0, 10.0), (30.0, 8.0), (0.25, 1000.0)):
+        b = oracle.subcell_burned([-1, -2, -3, -4], [100 - s] * 4, 100.0, T)
+        assert b == pytest.approx(1 - math.exp(-s / T), rel=1e-14)
+        assert b > 0
+
+
+def test_cell_fraction_no_fire_and_uniform_fire():
+    """F = 1 exactly when no stencil node burns; F = exp(-(t - t_i)/T_f)
+    (Eq. 4) when the whole stencil burns with one ignition time."""
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        p9 = rng.uniform(1e-3, 10, 9)
+        assert oracle.cell_frac(p9, np.full(9, 7.0), 7.0, 10.0) == 1.0
+    for s in (0.5, 3.0, 40.0):
+        p9 = -rng.uniform(1e-3, 10, 9)
+        F = oracle.cell_frac(p9, np.full(9, 20.0 - s), 20.0, 10.0)
+        assert F == pytest.approx(math.exp(-s / 10.0), rel=1e-14)
+
+
+def test_cell_fraction_second_order_whole_cell_burning():
+    """With the whole cell burning and t_i linear in space the quadrature
+    converges at second order to the exact cell average of
+    exp(-(t - t_i(x))/T_f) (Sect. 4.3)."""
+    T, t = 10.0, 50.0
+    gx, gy, t0 = 0.8, -0.5, 20.0            # t_i = t0 + gx x + gy y (s, x in m)
+    errs = []
+    for h in (4.0, 2.0, 1.0, 0.5):
+        X = np.array([-h, 0, h])
+        ti = t0 + gx * X[None, :] + gy * X[:, None]
+        F = oracle.cell_frac(-np.ones(9), ti, t, T)
+
+        def avg(g):
+            z = g * h / (2 * T)
+            return math.sinh(z) / z
+        exact = math.exp(-(t - t0) / T) * avg(gx) * avg(gy)
+        errs.append(abs(F - exact))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    assert all(1.9 < r < 2.1 for r in rates), rates
+
+
+# ------------------------------------------------------------- ignition
+
+def _brute_dist(x, y, ax, ay, bx, by, n=200001):
+    s = np.linspace(0, 1, n)
+    return np.min(np.hypot(x - (ax + s * (bx - ax)), y - (ay + s * (by - ay))))
+
+
+def test_ignition_geometry_brute_force():
+    """psi_g = dist(x, ab) - S_g (t - t_g), Eq. (20), against a brute-force
+    distance to densely sampled segment points; the arrival time is
+    t_g + dist/S_g (Sect. 4.4)."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        ax, ay, bx, by = rng.uniform(0, 100, 4)
+        g = synth.ignition(ax, ay, bx, by, t_start=2.0, radius=20.0, ros=0.5)
+        for _ in range(10):
+            x, y = rng.uniform(-20, 120, 2)
+            t = 2.0 + rng.uniform(0, 40)
+            p, a = oracle.ign_psi(g, x, y, t)
+            d = _brute_dist(x, y, ax, ay, bx, by)
+            L = math.hypot(bx - ax, by - ay)
+            assert p == pytest.approx(d - 0.5 * (t - 2.0), abs=2 * L / 200000 + 1e-12)
+            if p <= 0:
+                assert a == pytest.approx(2.0 + d / 0.5, abs=4 * L / 200000 + 1e-12)
+    # a point ignition is a segment of length 0
+    g = synth.ignition(3.0, 4.0, t_start=0.0, radius=5.0, ros=math.inf)
+    p, a = oracle.ign_psi(g, 0.0, 0.0, 0.0)
+    assert p == pytest.approx(0.0, abs=1e-15) and a == 0.0
+
+
+def test_ignition_window_and_drip_torch():
+    """Active for t_g <= t <= t_g + r_g/S_g (t_h + r_g/S_g for a drip torch);
+    the torch line is a -- a + v (min(t, t_h) - t_g) and the radius is capped
+    at r_g (Sect. 4.4)."""
+    g = synth.ignition(0, 0, 10, 0, t_start=5.0, radius=2.0, ros=0.5)
+    assert not oracle.ign_active(g, 4.99) and oracle.ign_active(g, 5.0)
+    assert oracle.ign_active(g, 9.0) and not oracle.ign_active(g, 9.01)
+    inst = synth.ignition(0, 0, t_start=5.0, radius=2.0)
+    assert oracle.ign_active(inst, 5.0) and not oracle.ign_active(inst, 5.1)
+    torch = synth.ignition(0, 0, t_start=1.0, radius=3.0, ros=0.5, vx=2.0, vy=0.0, t_end=11.0)
+    assert oracle.ign_active(torch, 16.9) and not oracle.ign_active(torch, 17.1)
+    rng = np.random.default_rng(2)
+    for _ in range(30):
+        t = rng.uniform(1.0, 16.0)
+        x, y = rng.uniform(-5, 30), rng.uniform(-8, 8)
+        end = 2.0 * (min(t, 11.0) - 1.0)
+        d = _brute_dist(x, y, 0, 0, end, 0)
+        p, a = oracle.ign_psi(torch, x, y, t)
+        assert p == pytest.approx(d - min(3.0, 0.5 * (t - 1.0)), abs=1e-3)
+        if p <= 0:
+            s = min(max(x, 0.0), end)              # nearest torch point on the x axis
+            assert a == pytest.approx(min(t, 1.0 + s / 2.0 + d / 0.5), abs=1e-3)

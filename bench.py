@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the fused fire-mesh time step on one MI355X.
+
+Default workload: the FP32 8192 x 8192 patchy fire (dx = 6 m, 13 Voronoi fuel
+categories, 8 Gaussian hills, 16-mode Fourier wind re-drawn every 10 steps
+from 4 fields resident in HBM, 4 line ignitions, dt = 0.25 s, refinement 10
+-> 820 x 820 atmosphere cells).  One step is one call of fire_step(): the
+whole method (ignition, both Heun stages, ignition times, fuel fraction,
+fluxes, atmosphere averaging) in one fused kernel launch.
+
+Prints one JSON line: cell-steps/s, the roofline of the step kernel measured
+with HIP events on the launch stream (algorithmic bytes 37 B per cell-step in
+FP32, 73 B in FP64, against 8 TB/s) and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+B_ALG = {"f32": 37.0, "f64": 73.0}   # bytes per cell-step the method must move
+KERNEL = "k_step"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import numpy as np
+    from paper_1102_1343_amd import synth
+    if name == "patchy8192":
+        p = synth.patchy_fire(n=8192, steps=1000, nwind=4, wind_period=10,
+                              field_dtype=np.float32)
+        return p, "f32"
+    if name == "patchy2048":
+        p = synth.patchy_fire(n=2048, steps=2000, field_dtype=np.float32)
+        return p, "f32"
+    if name == "uniform128":
+        return synth.uniform_fire(128), "f64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fire_kernels.hip", "fire_internal.h"):
+        with open(os.path.join(ROOT, "paper_1102_1343_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(name, dtype):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary for this workload, if it was taken on the current kernel
+    source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{name}_{dtype}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(prob, dtype, seconds):
+    """The FP64 oracle on a window of the same workload (1024 x 1024 cells
+    around the first ignition, the full mesh's initial level set), run for
+    whole steps until ``seconds`` of wall time have passed."""
+    import numpy as np
+    import oracle
+    from paper_1102_1343_amd import synth
+
+    w = min(1024, prob.nx)
+    h = min(1024, prob.ny)
+    g0 = prob.ignitions[0] if prob.ignitions else dict(ax=prob.nx * prob.dx / 2,
+                                                       ay=prob.ny * prob.dy / 2)
+    sr = prob.sr_x
+    i0 = int(min(max(0, g0["ax"] / prob.dx - w / 2), prob.nx - w)) // sr * sr
+    j0 = int(min(max(0, g0["ay"] / prob.dy - h / 2), prob.ny - h)) // prob.sr_y * prob.sr_y
+    win = synth.window(prob, i0, j0, w, h)
+    if dtype == "f32":
+        win = win.cast(np.float32)
+    psi0 = math.hypot(prob.nx * prob.dx, prob.ny * prob.dy)
+    o = oracle.OracleFire(win, psi_init=psi0)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(*win.wind_at(steps), win.dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds and steps >= 2:
+            break
+    return {"value": w * h * steps / el, "unit": "cell-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {w}x{h} window of the {prob.nx}x{prob.ny} workload at "
+                      f"({i0},{j0}), first {steps} steps from t=0, {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="patchy8192",
+                    choices=("patchy8192", "patchy2048", "uniform128"))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run 5 device copies of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.copy_probe_mib:
+        import torch
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "copies": 5}))
+        return 0
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(several GPUs would each own a 2-D block of the fire mesh with a halo "
+              "exchange every step, which is not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1102_1343_amd import fire as F
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+
+    log(f"generating workload {args.workload}")
+    t = time.perf_counter()
+    prob, dtype = workload(args.workload)
+    log(f"generated in {time.perf_counter() - t:.1f} s")
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    stream = torch.cuda.current_stream()
+    fire = F.Fire.from_problem(prob, dtype=tdt)
+    if args.tile:
+        fire.set_tile(*[int(x) for x in args.tile.split(",")])
+    winds = [(torch.from_numpy(np.ascontiguousarray(u)).to("cuda", tdt),
+              torch.from_numpy(np.ascontiguousarray(v)).to("cuda", tdt)) for u, v in prob.wind]
+    fs, fl = fire.new_flux()
+    torch.cuda.synchronize()
+    log(f"inputs resident; tile {fire.get_tile()}; warmup {args.warmup} steps")
+
+    def wind(k):
+        if prob.wind_period <= 0:
+            return winds[0]
+        return winds[(k // prob.wind_period) % len(winds)]
+
+    step = 0
+    for _ in range(args.warmup):
+        u, v = wind(step)
+        fire.step(u, v, prob.dt, fs, fl)
+        step += 1
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for k in range(K):
+        u, v = wind(step)
+        ev[k][0].record(stream)
+        fire.step(u, v, prob.dt, fs, fl)
+        ev[k][1].record(stream)
+        step += 1
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = t_start.elapsed_time(t_end)
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    elapsed = max(total_ms / 1e3, 1e-12)
+    cells = prob.nx * prob.ny
+    value = cells * K / elapsed
+    status = fire.status()
+    log(f"{K} steps in {elapsed * 1e3:.2f} ms (wall {wall * 1e3:.1f} ms), kernel avg "
+        f"{avg_kernel_s * 1e6:.1f} us, status {status}")
+
+    bytes_per_launch = B_ALG[dtype] * cells
+    achieved = bytes_per_launch / avg_kernel_s / 1e9
+    traffic = pmc_traffic(args.workload, dtype)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": KERNEL, "avg_kernel_us": round(avg_kernel_s * 1e6, 2),
+            "alg_bytes_per_cell_step": B_ALG[dtype]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (cpu_baseline)")
+        cpu = cpu_baseline(prob, dtype, args.cpu_seconds)
+        log(f"oracle {cpu['value']:.3e} cell-steps/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "fire cell-steps/s",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {prob.nx}x{prob.ny} fire mesh, dx={prob.dx} m, "
+                               f"{len(prob.fuels)} fuels, {len(prob.ignitions)} ignitions, "
+                               f"dt={prob.dt} s, refinement {prob.sr_x} "
+                               f"-> {fire.nax}x{fire.nay} atmosphere cells",
+                   "nx": prob.nx, "ny": prob.ny, "dt": prob.dt, "sr": prob.sr_x,
+                   "wind_fields": len(prob.wind), "wind_period": prob.wind_period,
+                   "tile": list(fire.get_tile()), "status": status},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,208 @@
+/*
+ * fire.h -- C ABI of the MI355X (gfx950) fire-mesh time step.
+ *
+ * The method is the fire module of WRF-Fire as described by Mandel, Beezley
+ * & Kochanski, "Coupled atmosphere-wildland fire modeling with WRF-Fire
+ * version 3.3" (arXiv:1102.1343).  One call of fire_step() makes one time
+ * step of the fire model in the order of Sect. 6:
+ *   1. ignition of active segment / drip-torch ignitions (Sect. 4.4,
+ *      Eqs. 20-21),
+ *   2. Heun step (Eq. 11) of the level-set equation (Eq. 10) with the
+ *      upwinded, viscous right-hand side of Eqs. (12)-(13), the spread rate
+ *      of Eq. (3) evaluated from the normal wind and slope, and the boundary
+ *      extrapolation of Sect. 4.1,
+ *   3. ignition times of nodes crossed during the step (Eq. 14),
+ *   4. fuel fraction by the sub-cell quadrature of Eqs. (15)-(19),
+ *   5. sensible and latent heat flux densities (Eqs. 5-6),
+ *   6. their mean over the fire cells of each atmosphere cell (Sect. 6),
+ * plus the boundary check of Sect. 4.1 (fire near the boundary ends the run).
+ *
+ * All per-cell arrays are device memory, row-major [ny][nx] with x fastest,
+ * cell (i, j) centred at ((i + 1/2) dx, (j + 1/2) dy).  Floating arrays have
+ * the element type chosen by fire_mesh.dtype (float or double).  Atmosphere
+ * arrays are [ceil(ny/sr_y)][ceil(nx/sr_x)].
+ *
+ * Ownership: the caller owns every device buffer -- inputs, the state arena
+ * and the outputs.  The library owns only the context (host memory) and
+ * allocates no device memory.  Every call is asynchronous on the context's
+ * stream unless stated otherwise; no function throws.
+ *
+ * Errors: functions return FIRE_OK (0) or a negative FIRE_ERR_* code;
+ * fire_strerror() names it.  Argument errors are detected before anything is
+ * enqueued.  Errors of earlier asynchronous work surface as FIRE_ERR_HIP from
+ * a later call.
+ */
+#ifndef FIRE_H
+#define FIRE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FIRE_ABI_VERSION 1
+
+enum {
+    FIRE_OK = 0,
+    FIRE_ERR_ARG = -1,       /* invalid argument (size, pointer, value)      */
+    FIRE_ERR_HIP = -2,       /* a HIP runtime call or kernel launch failed   */
+    FIRE_ERR_OOM = -3,       /* host allocation of the context failed        */
+    FIRE_ERR_BOUNDARY = -4,  /* fire reached the guard ring (Sect. 4.1)      */
+    FIRE_ERR_NONFINITE = -5, /* non-finite level set or fuel fraction        */
+    FIRE_ERR_STATE = -6      /* call not allowed in the context's state      */
+};
+
+/* sticky status bits reported by fire_status() */
+enum { FIRE_STATUS_BOUNDARY = 1, FIRE_STATUS_NONFINITE = 2 };
+
+typedef enum { FIRE_F32 = 0, FIRE_F64 = 1 } fire_dtype;
+
+/* Fire mesh (Sect. 3): nx x ny cells of dx x dy metres; sr_x x sr_y fire
+ * cells make one atmosphere cell (refinement ratio, Sect. 8.2).  Needs
+ * nx, ny >= 2, 1 <= sr_x <= 122, 1 <= sr_y <= 26. */
+typedef struct {
+    int32_t nx, ny;
+    double dx, dy;
+    int32_t sr_x, sr_y;
+    int32_t dtype;            /* fire_dtype */
+    int32_t reserved;
+} fire_mesh;
+
+/* One fuel category: the quantities of Table 1 in SI units. */
+typedef struct {
+    double windrf;            /* a, wind reduction from 6.1 m to midflame     */
+    double tf;                /* T_f (s); if <= 0, T_f = -600 w/(1000 ln 0.6) */
+    double weight;            /* w (s), used only when tf <= 0 (Eq. 4)        */
+    double fgi;               /* w_l total fuel load (kg/m^2)                 */
+    double fueldepthm;        /* delta (m)                                    */
+    double savr;              /* sigma, surface/volume ratio (1/m)            */
+    double fuelmce;           /* M_x, moisture of extinction                  */
+    double fueldens;          /* rho_P, oven-dry particle density (kg/m^3)    */
+    double st;                /* S_T, total mineral content                   */
+    double se;                /* S_E, effective mineral content               */
+    double cmbcnst;           /* h, heat content of dry fuel (J/kg)           */
+    double fuelmc_g;          /* M_f, fuel moisture content                   */
+    double ros_mult;          /* per-category spread multiplier m_k (1)       */
+    int32_t ichap;            /* non-zero: chaparral spread rate, Eq. (2)     */
+    int32_t reserved;
+} fire_fuel;
+
+/* Ignition (Sect. 4.4).  Segment a-b (a point when a == b) started at t_start
+ * with initial spread rate ros until the distance radius is reached; with
+ * (vx, vy) != 0 a drip torch starting at a with velocity v until t_end
+ * (b unused).  ros = +inf ignites the disc of the given radius at once, in
+ * the step that starts exactly at t_start. */
+typedef struct {
+    double ax, ay, bx, by;    /* m                                            */
+    double t_start;           /* t_g (s)                                      */
+    double radius;            /* r_g (m)                                      */
+    double ros;               /* S_g (m/s)                                    */
+    double vx, vy;            /* drip-torch velocity (m/s)                    */
+    double t_end;             /* t_h (s)                                      */
+} fire_ignition;
+
+#define FIRE_MAX_IGNITIONS 8
+
+typedef struct {
+    double viscosity;         /* epsilon of Eq. (12), 0.4 in the paper        */
+    double psi_init;          /* initial level set (> 0); <= 0: domain diagonal */
+    double wind_cap;          /* e of Eq. (3) for Rothermel fuels (30 m/s)    */
+    double ros_cap;           /* upper cap on S (m/s); +inf for none          */
+    double t0;                /* initial time (s)                             */
+    int32_t guard_width;      /* guard ring width (cells) of the boundary check */
+    int32_t boundary_policy;  /* 0: stop at fire in the guard ring, 1: continue */
+    int32_t viscosity_mode;   /* 0: eps*S*Lap~ psi; 1: eps*Lap~ psi (literal) */
+    int32_t reserved;
+} fire_params;
+
+typedef struct fire_ctx fire_ctx;
+
+/* Device pointers into the state arena and the model time. */
+typedef struct {
+    const void *psi;          /* level set psi [ny][nx]                       */
+    const void *tign;         /* ignition time t_i [ny][nx], +inf = not yet   */
+    const void *frac;         /* fuel fraction F [ny][nx]                     */
+    double t;                 /* model time of this state (s)                 */
+} fire_view;
+
+/* Bytes of caller-owned device memory the state arena needs for this mesh
+ * and number of fuel categories (psi double buffer, t_i, F, coefficient
+ * table, status word).  Returns 0 for an invalid mesh. */
+size_t fire_state_bytes(const fire_mesh *mesh, int32_t ncat);
+
+/*
+ * Create a context and initialise the state (Sect. 4.4): psi = psi_init,
+ * t_i = +inf, F = 1, time t0.  The per-category spread-rate coefficients of
+ * Eqs. (1)-(3) / Table 2, the burn time of Eq. (4) and the flux factors of
+ * Eqs. (5)-(6) are computed on the device into the arena.
+ *   mesh, cats[ncat], ign[nign], prm : host structs, copied
+ *   fuel_cat : device uint8 [ny][nx], values < ncat (checked by the caller)
+ *   dzdx, dzdy : device [ny][nx] terrain gradient (Sect. 6, preprocessing)
+ *   state : device arena of at least fire_state_bytes(), 256-byte aligned
+ *   stream : hipStream_t (NULL = default stream)
+ * fuel_cat, dzdx, dzdy and state must stay valid until fire_destroy().
+ * 1 <= ncat <= 256, 0 <= nign <= FIRE_MAX_IGNITIONS.
+ */
+int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int32_t ncat,
+              const uint8_t *fuel_cat, const void *dzdx, const void *dzdy,
+              const fire_ignition *ign, int32_t nign, const fire_params *prm,
+              void *state, size_t state_bytes, void *stream);
+
+/*
+ * One fire time step of length dt (> 0) driven by the surface wind (u, v)
+ * (device [ny][nx], m/s at 6.1 m, on fire cell centres).  Writes the mean
+ * sensible and latent heat flux densities (W/m^2) over the step into
+ * flux_sens / flux_lat (device atmosphere arrays) and updates the state in
+ * the arena.  If out is not NULL it receives device pointers to the new
+ * psi, t_i and F (valid until the next fire_step) and the new time.
+ * With boundary_policy 0 the call waits for the step and returns
+ * FIRE_ERR_BOUNDARY if fire reached the guard ring; later calls then do
+ * nothing and return FIRE_ERR_BOUNDARY.  With policy 1 nothing waits and the
+ * condition is only recorded in the status word.
+ */
+int fire_step(fire_ctx *ctx, const void *u, const void *v, double dt, void *flux_sens,
+              void *flux_lat, fire_view *out);
+
+/* Current state pointers and time (no copy). */
+int fire_get_state(fire_ctx *ctx, fire_view *out);
+
+/* Replace the state by device copies of psi, t_i and F (each [ny][nx]) and
+ * set the time (checkpoint restore).  The status word is cleared. */
+int fire_set_state(fire_ctx *ctx, const void *psi, const void *tign, const void *frac, double t);
+
+/* Waits for the context's stream and returns the sticky FIRE_STATUS_* bits
+ * (>= 0), or a negative error code. */
+int fire_status(fire_ctx *ctx);
+
+/* Copies the per-category coefficient table to host memory (waits):
+ * out[ncat][10] as doubles, columns S0 R0 b c d e m T_f C_h C_q. */
+int fire_coef(fire_ctx *ctx, double *out, int32_t ncat);
+
+/* Spread rate of Eq. (3) for n points (test entry): S[k] from category
+ * cat[k], normal wind un[k] and normal slope tn[k] (device arrays of the
+ * context dtype).  Asynchronous. */
+int fire_ros_eval(fire_ctx *ctx, const uint8_t *cat, const void *un, const void *tn, void *S,
+                  int64_t n);
+
+/* Tile shape of the fused step kernel: tile_x a multiple of sr_x with
+ * tile_x <= 122, tile_y a multiple of sr_y with tile_y <= 26.  Results do not
+ * depend on the tile shape. */
+int fire_set_tile(fire_ctx *ctx, int32_t tile_x, int32_t tile_y);
+int fire_get_tile(fire_ctx *ctx, int32_t *tile_x, int32_t *tile_y);
+
+/* Change the stream later calls enqueue on. */
+int fire_set_stream(fire_ctx *ctx, void *stream);
+
+const char *fire_strerror(int code);
+int fire_abi_version(void);
+
+/* Releases the context (no device memory is freed: the caller owns it). */
+void fire_destroy(fire_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIRE_H */

@@ -88,6 +88,7 @@ def lib():
         L.oracle_step.argtypes = [C.POINTER(_Mesh), dp, C.c_int, C.POINTER(C.c_uint8), dp, dp,
                                   dp, dp, C.POINTER(_Ign), C.c_int, C.POINTER(_Prm), C.c_double,
                                   C.c_double, dp, dp, dp, dp, dp, C.POINTER(C.c_int32)]
+        L.oracle_threads.restype = C.c_int
         assert L.oracle_sizeof_fuel() == C.sizeof(_Fuel)
         assert L.oracle_sizeof_ign() == C.sizeof(_Ign)
         assert L.oracle_ncoef() == NCOEF
@@ -116,6 +117,11 @@ def _igns(igns):
         for name, _ in _Ign._fields_:
             setattr(arr[k], name, float(g[name]))
     return arr
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_threads())
 
 
 # ---------------------------------------------------------------- pieces

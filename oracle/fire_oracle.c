@@ -43,6 +43,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---- data passed in from the Python wrapper (layouts mirrored there) ---- */
 
@@ -92,6 +95,14 @@ enum { OC_S0, OC_R0, OC_B, OC_C, OC_D, OC_E, OC_M, OC_TF, OC_CH, OC_CQ, OC_N };
 enum { OS_BOUNDARY = 1, OS_NONFINITE = 2 };
 
 int oracle_ncoef(void) { return OC_N; }
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 int oracle_sizeof_fuel(void) { return (int)sizeof(of_fuel); }
 int oracle_sizeof_ign(void) { return (int)sizeof(of_ign); }
 

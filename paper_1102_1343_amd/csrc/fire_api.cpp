@@ -1,0 +1,349 @@
+// C ABI of the fire-mesh step library: argument checking, the state arena
+// layout, the fire time bookkeeping and kernel launches.  Every piece of the
+// method's arithmetic runs in the kernels of fire_kernels.hip.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "fire_internal.h"
+
+using namespace fire;
+
+struct fire_ctx {
+    fire_mesh mesh;
+    fire_params prm;
+    int ncat;
+    int nign;
+    fire_ignition ign[FIRE_MAX_IGNITIONS];
+    const uint8_t *cat;
+    const void *dzdx, *dzdy;
+    char *arena;
+    size_t off_coef, off_fuel, off_status, off_psi[2], off_tign, off_frac;
+    int cur;               // index of the current psi buffer
+    double t;              // model time of the current state
+    hipStream_t stream;
+    int tile_x, tile_y;
+    int stopped;           // boundary reached under the stop policy
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t esize(const fire_mesh *m) { return m->dtype == FIRE_F64 ? 8 : 4; }
+
+bool mesh_ok(const fire_mesh *m) {
+    if (!m) return false;
+    if (m->nx < 2 || m->ny < 2) return false;
+    if ((int64_t)m->nx * m->ny > ((int64_t)1 << 31)) return false;
+    if (!(m->dx > 0.0) || !(m->dy > 0.0) || !std::isfinite(m->dx) || !std::isfinite(m->dy))
+        return false;
+    if (m->sr_x < 1 || m->sr_x > kTileXMax || m->sr_y < 1 || m->sr_y > kTileYMax) return false;
+    return m->dtype == FIRE_F32 || m->dtype == FIRE_F64;
+}
+
+struct Layout {
+    size_t coef, fuel, status, psi0, psi1, tign, frac, total;
+};
+
+Layout layout(const fire_mesh *m, int ncat) {
+    const size_t n = (size_t)m->nx * m->ny, e = esize(m);
+    Layout L;
+    size_t o = 0;
+    L.coef = o;
+    o = align_up(o + (size_t)ncat * kNCoef * e);
+    L.fuel = o;
+    o = align_up(o + (size_t)ncat * sizeof(fire_fuel));
+    L.status = o;
+    o = align_up(o + 64);
+    L.psi0 = o;
+    o = align_up(o + n * e);
+    L.psi1 = o;
+    o = align_up(o + n * e);
+    L.tign = o;
+    o = align_up(o + n * e);
+    L.frac = o;
+    o = align_up(o + n * e);
+    L.total = o;
+    return L;
+}
+
+// default tile: widest multiple of sr_x that fits the frame, and the
+// tallest multiple of sr_y up to 20 rows (26 when sr_y does not divide 20)
+void default_tile(const fire_mesh *m, int *tx, int *ty) {
+    *tx = (kTileXMax / m->sr_x) * m->sr_x;
+    int best = 0;
+    for (int h = m->sr_y; h <= kTileYMax; h += m->sr_y)
+        if (h <= 20) best = h;
+    if (best == 0) best = (kTileYMax / m->sr_y) * m->sr_y;
+    *ty = best;
+}
+
+int hip_fail(hipError_t e) { return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP; }
+
+void *state_ptr(fire_ctx *c, size_t off) { return c->arena + off; }
+
+}  // namespace
+
+extern "C" {
+
+int fire_abi_version(void) { return FIRE_ABI_VERSION; }
+
+const char *fire_strerror(int code) {
+    switch (code) {
+    case FIRE_OK: return "ok";
+    case FIRE_ERR_ARG: return "invalid argument";
+    case FIRE_ERR_HIP: return "HIP runtime or kernel launch error";
+    case FIRE_ERR_OOM: return "host allocation failed";
+    case FIRE_ERR_BOUNDARY: return "fire reached the domain boundary guard ring";
+    case FIRE_ERR_NONFINITE: return "non-finite level set or fuel fraction";
+    case FIRE_ERR_STATE: return "call not allowed in the current context state";
+    default: return "unknown error";
+    }
+}
+
+size_t fire_state_bytes(const fire_mesh *mesh, int32_t ncat) {
+    if (!mesh_ok(mesh) || ncat < 1 || ncat > 256) return 0;
+    return layout(mesh, ncat).total;
+}
+
+int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int32_t ncat,
+              const uint8_t *fuel_cat, const void *dzdx, const void *dzdy,
+              const fire_ignition *ign, int32_t nign, const fire_params *prm, void *state,
+              size_t state_bytes, void *stream) {
+    if (!out) return FIRE_ERR_ARG;
+    *out = nullptr;
+    if (!mesh_ok(mesh) || !cats || ncat < 1 || ncat > 256 || !fuel_cat || !dzdx || !dzdy ||
+        !prm || !state || nign < 0 || nign > FIRE_MAX_IGNITIONS || (nign > 0 && !ign))
+        return FIRE_ERR_ARG;
+    if (((uintptr_t)state % kAlign) != 0) return FIRE_ERR_ARG;
+    const Layout L = layout(mesh, ncat);
+    if (state_bytes < L.total) return FIRE_ERR_ARG;
+    if (!(prm->viscosity >= 0.0) || !std::isfinite(prm->viscosity)) return FIRE_ERR_ARG;
+    if (!(prm->wind_cap > 0.0) || !(prm->ros_cap > 0.0) || !std::isfinite(prm->t0))
+        return FIRE_ERR_ARG;
+    if (prm->guard_width < 0 || (prm->boundary_policy != 0 && prm->boundary_policy != 1) ||
+        (prm->viscosity_mode != 0 && prm->viscosity_mode != 1))
+        return FIRE_ERR_ARG;
+    for (int k = 0; k < ncat; k++) {
+        const fire_fuel &f = cats[k];
+        if (!(f.ros_mult >= 0.0)) return FIRE_ERR_ARG;
+        if (!(f.tf > 0.0) && !(f.weight > 0.0)) return FIRE_ERR_ARG;
+        if (!f.ichap && !(f.fgi > 0.0 && f.fueldepthm > 0.0 && f.savr > 0.0 && f.fuelmce > 0.0 &&
+                          f.fueldens > 0.0 && f.se > 0.0 && f.fuelmc_g >= 0.0))
+            return FIRE_ERR_ARG;
+    }
+    for (int g = 0; g < nign; g++) {
+        const fire_ignition &r = ign[g];
+        if (!(r.ros > 0.0) || !(r.radius >= 0.0) || !std::isfinite(r.radius) ||
+            !std::isfinite(r.t_start))
+            return FIRE_ERR_ARG;
+        if ((r.vx != 0.0 || r.vy != 0.0) && !(r.t_end >= r.t_start)) return FIRE_ERR_ARG;
+    }
+
+    fire_ctx *c = new (std::nothrow) fire_ctx();
+    if (!c) return FIRE_ERR_OOM;
+    c->mesh = *mesh;
+    c->prm = *prm;
+    c->ncat = ncat;
+    c->nign = nign;
+    for (int g = 0; g < nign; g++) c->ign[g] = ign[g];
+    c->cat = fuel_cat;
+    c->dzdx = dzdx;
+    c->dzdy = dzdy;
+    c->arena = (char *)state;
+    c->off_coef = L.coef;
+    c->off_fuel = L.fuel;
+    c->off_status = L.status;
+    c->off_psi[0] = L.psi0;
+    c->off_psi[1] = L.psi1;
+    c->off_tign = L.tign;
+    c->off_frac = L.frac;
+    c->cur = 0;
+    c->t = prm->t0;
+    c->stream = (hipStream_t)stream;
+    c->stopped = 0;
+    default_tile(mesh, &c->tile_x, &c->tile_y);
+
+    // the fuel table goes through the arena (it may exceed kernel-argument
+    // space); the copy is synchronous because cats is pageable host memory
+    hipError_t e = hipMemcpyAsync(state_ptr(c, L.fuel), cats, sizeof(fire_fuel) * ncat,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = launch_coef(mesh->dtype, (const fire_fuel *)state_ptr(c, L.fuel), ncat, prm->wind_cap,
+                        state_ptr(c, L.coef), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(state_ptr(c, L.status), 0, 64, c->stream);
+    double psi0 = prm->psi_init;
+    if (!(psi0 > 0.0))
+        psi0 = std::sqrt((mesh->nx * mesh->dx) * (mesh->nx * mesh->dx) +
+                         (mesh->ny * mesh->dy) * (mesh->ny * mesh->dy));
+    if (e == hipSuccess)
+        e = launch_fill(mesh->dtype, state_ptr(c, L.psi0), state_ptr(c, L.tign),
+                        state_ptr(c, L.frac), (size_t)mesh->nx * mesh->ny, psi0, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return FIRE_ERR_HIP;
+    }
+    *out = c;
+    return FIRE_OK;
+}
+
+int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_sens,
+              void *flux_lat, fire_view *out) {
+    if (!c || !u || !v || !flux_sens || !flux_lat) return FIRE_ERR_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return FIRE_ERR_ARG;
+    if (c->stopped) return FIRE_ERR_BOUNDARY;
+    const fire_mesh &m = c->mesh;
+
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = m.nx;
+    a.ny = m.ny;
+    a.tile_x = c->tile_x;
+    a.tile_y = c->tile_y;
+    a.tiles_x = (m.nx + c->tile_x - 1) / c->tile_x;
+    const int tiles_y = (m.ny + c->tile_y - 1) / c->tile_y;
+    a.ntiles = a.tiles_x * tiles_y;
+    a.per_xcd = (a.ntiles + 7) / 8;
+    a.sr_x = m.sr_x;
+    a.sr_y = m.sr_y;
+    a.nax = (m.nx + m.sr_x - 1) / m.sr_x;
+    a.nay = (m.ny + m.sr_y - 1) / m.sr_y;
+    a.ncat = c->ncat;
+    a.guard = c->prm.guard_width;
+    a.visc_mode = c->prm.viscosity_mode;
+    a.nign = c->nign;
+    a.dx = m.dx;
+    a.dy = m.dy;
+    a.t = c->t;
+    a.dt = dt;
+    a.eps = c->prm.viscosity;
+    a.ros_cap = c->prm.ros_cap;
+    for (int g = 0; g < c->nign; g++) a.ign[g] = c->ign[g];
+
+    StepBuffers b;
+    b.psi_in = state_ptr(c, c->off_psi[c->cur]);
+    b.psi_out = state_ptr(c, c->off_psi[1 - c->cur]);
+    b.tign = state_ptr(c, c->off_tign);
+    b.frac = state_ptr(c, c->off_frac);
+    b.u = u;
+    b.v = v;
+    b.dzdx = c->dzdx;
+    b.dzdy = c->dzdy;
+    b.cat = c->cat;
+    b.coef = state_ptr(c, c->off_coef);
+    b.fsens = flux_sens;
+    b.flat = flux_lat;
+    b.status = (int *)state_ptr(c, c->off_status);
+
+    hipError_t e = launch_step(m.dtype, a, b, c->stream);
+    if (e != hipSuccess) return FIRE_ERR_HIP;
+    c->cur = 1 - c->cur;
+    c->t += dt;
+    if (out) {
+        out->psi = state_ptr(c, c->off_psi[c->cur]);
+        out->tign = b.tign;
+        out->frac = b.frac;
+        out->t = c->t;
+    }
+    if (c->prm.boundary_policy == 0) {
+        // Sect. 4.1: the run terminates when fire reaches the boundary
+        int st = fire_status(c);
+        if (st < 0) return st;
+        if (st & FIRE_STATUS_BOUNDARY) {
+            c->stopped = 1;
+            return FIRE_ERR_BOUNDARY;
+        }
+    }
+    return FIRE_OK;
+}
+
+int fire_get_state(fire_ctx *c, fire_view *out) {
+    if (!c || !out) return FIRE_ERR_ARG;
+    out->psi = state_ptr(c, c->off_psi[c->cur]);
+    out->tign = state_ptr(c, c->off_tign);
+    out->frac = state_ptr(c, c->off_frac);
+    out->t = c->t;
+    return FIRE_OK;
+}
+
+int fire_set_state(fire_ctx *c, const void *psi, const void *tign, const void *frac, double t) {
+    if (!c || !psi || !tign || !frac || !std::isfinite(t)) return FIRE_ERR_ARG;
+    const size_t bytes = (size_t)c->mesh.nx * c->mesh.ny * esize(&c->mesh);
+    hipError_t e = hipMemcpyAsync(state_ptr(c, c->off_psi[c->cur]), psi, bytes,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(state_ptr(c, c->off_tign), tign, bytes, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(state_ptr(c, c->off_frac), frac, bytes, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(state_ptr(c, c->off_status), 0, 64, c->stream);
+    if (e != hipSuccess) return FIRE_ERR_HIP;
+    c->t = t;
+    c->stopped = 0;
+    return FIRE_OK;
+}
+
+int fire_status(fire_ctx *c) {
+    if (!c) return FIRE_ERR_ARG;
+    int32_t st = 0;
+    hipError_t e = hipMemcpyAsync(&st, state_ptr(c, c->off_status), sizeof(st),
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return FIRE_ERR_HIP;
+    return st & (FIRE_STATUS_BOUNDARY | FIRE_STATUS_NONFINITE);
+}
+
+int fire_coef(fire_ctx *c, double *out, int32_t ncat) {
+    if (!c || !out || ncat != c->ncat) return FIRE_ERR_ARG;
+    // widened into the fuel staging area (no longer needed after init; a
+    // fuel record is larger than a row of doubles), then copied out
+    static_assert(sizeof(fire_fuel) >= kNCoef * sizeof(double), "staging area too small");
+    const int n = c->ncat * kNCoef;
+    double *stage = (double *)state_ptr(c, c->off_fuel);
+    hipError_t e = launch_coef_to_f64(c->mesh.dtype, state_ptr(c, c->off_coef), stage, n,
+                                      c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, stage, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_fail(e);
+}
+
+int fire_ros_eval(fire_ctx *c, const uint8_t *cat, const void *un, const void *tn, void *S,
+                  int64_t n) {
+    if (!c || n < 0 || (n > 0 && (!cat || !un || !tn || !S))) return FIRE_ERR_ARG;
+    if (n == 0) return FIRE_OK;
+    return hip_fail(launch_ros_eval(c->mesh.dtype, state_ptr(c, c->off_coef), c->ncat,
+                                    c->prm.ros_cap, cat, un, tn, S, n, c->stream));
+}
+
+int fire_set_tile(fire_ctx *c, int32_t tile_x, int32_t tile_y) {
+    if (!c) return FIRE_ERR_ARG;
+    if (tile_x < 1 || tile_x > kTileXMax || tile_x % c->mesh.sr_x != 0) return FIRE_ERR_ARG;
+    if (tile_y < 1 || tile_y > kTileYMax || tile_y % c->mesh.sr_y != 0) return FIRE_ERR_ARG;
+    c->tile_x = tile_x;
+    c->tile_y = tile_y;
+    return FIRE_OK;
+}
+
+int fire_get_tile(fire_ctx *c, int32_t *tile_x, int32_t *tile_y) {
+    if (!c || !tile_x || !tile_y) return FIRE_ERR_ARG;
+    *tile_x = c->tile_x;
+    *tile_y = c->tile_y;
+    return FIRE_OK;
+}
+
+int fire_set_stream(fire_ctx *c, void *stream) {
+    if (!c) return FIRE_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    return FIRE_OK;
+}
+
+void fire_destroy(fire_ctx *c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,621 @@
+// HIP kernels (gfx950, wave64) of the WRF-Fire fire-mesh time step
+// (Mandel, Beezley & Kochanski, arXiv:1102.1343).
+//
+// k_step is the whole step fused into one pass over the mesh: a work-group
+// loads its tile plus three halo rings into LDS once, applies the ignitions
+// (Sect. 4.4), runs both Heun stages of the level-set equation (Eqs. 10-13)
+// with the boundary extrapolation of Sect. 4.1 redone for each stage, sets
+// the ignition times (Eq. 14), integrates the fuel fraction over sub-cells
+// (Eqs. 15-19), forms the heat fluxes (Eqs. 5-6) and averages them over the
+// atmosphere cells of the tile (Sect. 6).  Tiles are multiples of the
+// refinement ratio, so every atmosphere cell is reduced inside one
+// work-group in a fixed order: no atomics, bitwise reproducible.
+//
+// HBM traffic per cell and step is one read of psi, t_i, F, u, v, dz/dx,
+// dz/dy, category and one write of psi and F (t_i only where it changes);
+// halo re-reads come from L2.  Work-groups are remapped so that each of the
+// eight XCDs sweeps a contiguous band of tiles, keeping halo rows in its L2.
+#include "fire_internal.h"
+
+#include <cmath>
+
+namespace fire {
+namespace {
+
+// ---------------------------------------------------------------- math
+template <typename T> struct M;
+
+template <> struct M<float> {
+    // x >= 0; x = 0 gives 0 for b > 0
+    static __device__ __forceinline__ float powp(float x, float b) {
+        return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(x));
+    }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) {
+        return a * __builtin_amdgcn_rcpf(b);
+    }
+    // 1 - exp(-x) without cancellation for small x
+    static __device__ __forceinline__ float one_m_exp_neg(float x) { return -expm1f(-x); }
+    static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+};
+
+template <> struct M<double> {
+    static __device__ __forceinline__ double powp(double x, double b) { return ::pow(x, b); }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double one_m_exp_neg(double x) { return -::expm1(-x); }
+    static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+};
+
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+template <typename T> __device__ __forceinline__ bool is_inf(T a) { return a == M<T>::inf(); }
+
+// Spread rate, Eq. (3), with the category multiplier and the cap:
+// S = min{cap, m max{S0, R0 + c min{e, max{0,U}}^b + d max{0, tan phi}^2}}.
+template <typename T>
+__device__ __forceinline__ T ros(const T *row, T un, T tn, T cap) {
+    T U = un > T(0) ? un : T(0);
+    U = U > row[kE] ? row[kE] : U;
+    T g = tn > T(0) ? tn : T(0);
+    T s = row[kR0] + row[kC] * M<T>::powp(U, row[kB]) + row[kD] * g * g;
+    s = s < row[kS0] ? row[kS0] : s;
+    s = row[kM] * s;
+    return s > cap ? cap : s;
+}
+
+// Godunov upwind selection of Eq. (13), cases taken in the printed order.
+template <typename T> __device__ __forceinline__ T godunov(T dm, T dp) {
+    if (dm <= T(0) && dp <= T(0)) return dp;
+    if (dm >= T(0) && dp >= T(0)) return dm;
+    if (dm <= T(0) && dp >= T(0)) return T(0);
+    return tabs(dm) >= tabs(dp) ? dm : dp;
+}
+
+// Boundary extrapolation of Sect. 4.1: never below either source node.
+template <typename T> __device__ __forceinline__ T ghost(T pb, T pb1) {
+    T lin = pb + (pb - pb1);
+    T m = pb > pb1 ? pb : pb1;
+    return lin > m ? lin : m;
+}
+
+template <typename T> struct Consts {
+    T dx, dy, rdx, rdy, r2dx, r2dy, eps, cap;
+    int visc_mode;
+};
+
+// Right-hand side of Eq. (12) at frame cell (fy, fx) of the level set P.
+template <typename T>
+__device__ __forceinline__ T rhs(const T (*P)[kFW], int fy, int fx, T u, T v, T gzx, T gzy,
+                                 const T *row, const Consts<T> &c) {
+    const T pc = P[fy][fx], pw = P[fy][fx - 1], pe = P[fy][fx + 1];
+    const T ps = P[fy - 1][fx], pn = P[fy + 1][fx];
+    const T gx = godunov((pc - pw) * c.rdx, (pe - pc) * c.rdx);
+    const T gy = godunov((pc - ps) * c.rdy, (pn - pc) * c.rdy);
+    const T up = M<T>::sqrt(gx * gx + gy * gy);
+    // normal from central differences; zero where the gradient vanishes
+    const T cx = (pe - pw) * c.r2dx, cy = (pn - ps) * c.r2dy;
+    const T cn2 = cx * cx + cy * cy;
+    T nx = T(0), ny = T(0);
+    if (cn2 > T(0)) {
+        const T inv = M<T>::rsqrt(cn2);
+        nx = cx * inv;
+        ny = cy * inv;
+    }
+    const T S = ros(row, u * nx + v * ny, gzx * nx + gzy * ny, c.cap);
+    const T lap = (pe - T(2) * pc + pw) * c.rdx + (pn - T(2) * pc + ps) * c.rdy;
+    const T visc = c.visc_mode == 0 ? c.eps * S * lap : c.eps * lap;
+    return visc - S * up;
+}
+
+// One ignition's geometry at time t.  The segment start stays in double so
+// node offsets are formed exactly from global coordinates: psi_g at a node
+// is then the same in every tile that touches the node (owner or halo).
+template <typename T> struct IgnGeo {
+    double ax, ay;
+    T ex, ey, invL2, rad, tg, lenv, invS, t;
+};
+
+template <typename T>
+__device__ __forceinline__ bool ign_setup(const fire_ignition &g, double t, IgnGeo<T> &o) {
+    const bool torch = (g.vx != 0.0 || g.vy != 0.0);
+    const double tend = torch ? g.t_end : g.t_start;
+    const bool inst = __builtin_isinf(g.ros);
+    const double grow = inst ? 0.0 : g.radius / g.ros;
+    if (!(t >= g.t_start && t <= tend + grow)) return false;
+    double bx = g.bx, by = g.by;
+    if (torch) {
+        const double te = t < g.t_end ? t : g.t_end;
+        bx = g.ax + g.vx * (te - g.t_start);
+        by = g.ay + g.vy * (te - g.t_start);
+    }
+    const double ex = bx - g.ax, ey = by - g.ay;
+    const double L2 = ex * ex + ey * ey;
+    const double r = g.ros * (t - g.t_start);
+    o.ax = g.ax;
+    o.ay = g.ay;
+    o.ex = T(ex);
+    o.ey = T(ey);
+    o.invL2 = L2 > 0.0 ? T(1.0 / L2) : T(0);
+    o.rad = T(inst ? g.radius : (r < g.radius ? r : g.radius));
+    o.tg = T(g.t_start);
+    o.lenv = torch ? T(::sqrt(L2) / ::sqrt(g.vx * g.vx + g.vy * g.vy)) : T(0);
+    o.invS = inst ? T(0) : T(1.0 / g.ros);
+    o.t = T(t);
+    return true;
+}
+
+// psi_g of Eq. (20) (drip-torch form) at the node centred at (x, y) (global
+// metres, double), and the arrival time of the initial fire there, capped
+// at t.
+template <typename T>
+__device__ __forceinline__ T ign_psi(const IgnGeo<T> &g, double x, double y, T &arrive) {
+    const T px = T(x - g.ax), py = T(y - g.ay);
+    T s = (px * g.ex + py * g.ey) * g.invL2;
+    s = s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+    const T qx = px - s * g.ex, qy = py - s * g.ey;
+    const T d = M<T>::sqrt(qx * qx + qy * qy);
+    const T a = g.tg + s * g.lenv + d * g.invS;
+    arrive = a < g.t ? a : g.t;
+    return d - g.rad;
+}
+
+// Fill the one-cell ghost ring of frame P around the domain (Sect. 4.1).
+// Ghost nodes read in-domain nodes only, so the ring fills in one pass.
+// Corners (x and y outside) are the x extrapolation of the ghost row.
+template <typename T>
+__device__ __forceinline__ void ghost_node(T (*P)[kFW], int fy, int fx, int gx, int gy, int nx,
+                                           int ny, bool corners) {
+    const bool xin = gx >= 0 && gx < nx, yin = gy >= 0 && gy < ny;
+    const int sx = gx == -1 ? 1 : (gx == nx ? -1 : 0);
+    const int sy = gy == -1 ? 1 : (gy == ny ? -1 : 0);
+    if (yin && sx != 0) {
+        P[fy][fx] = ghost(P[fy][fx + sx], P[fy][fx + 2 * sx]);
+    } else if (xin && sy != 0) {
+        P[fy][fx] = ghost(P[fy + sy][fx], P[fy + 2 * sy][fx]);
+    } else if (corners && sx != 0 && sy != 0) {
+        const T r1 = ghost(P[fy + sy][fx + sx], P[fy + 2 * sy][fx + sx]);
+        const T r2 = ghost(P[fy + sy][fx + 2 * sx], P[fy + 2 * sy][fx + 2 * sx]);
+        P[fy][fx] = ghost(r1, r2);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
+       const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
+       const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
+       T *__restrict__ fsens, T *__restrict__ flat, int *status) {
+    __shared__ T A[kFHMax][kFW];
+    __shared__ T B[kFHMax][kFW];
+    extern __shared__ double dyn_smem[];
+    T *tab = reinterpret_cast<T *>(dyn_smem);
+
+    // XCD-aware tile order: work-group b runs on XCD b % 8; give each XCD a
+    // contiguous range of row-major tiles.
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (tile >= a.ntiles) return;
+    const int tyi = tile / a.tiles_x;
+    const int txi = tile - tyi * a.tiles_x;
+    const int x0 = txi * a.tile_x, y0 = tyi * a.tile_y;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * kFW + tx;
+    const int nx = a.nx, ny = a.ny;
+    const int FH = a.tile_y + 2 * kHalo;
+    const int gx = x0 - kHalo + tx;
+    const bool colin = gx >= 0 && gx < nx;
+    const bool xr1 = tx >= 1 && tx < a.tile_x + 5;
+    const bool xr2 = tx >= 2 && tx < a.tile_x + 4;
+    const bool xr3 = tx >= 3 && tx < a.tile_x + 3;
+
+    for (int i = tid; i < a.ncat * kNCoef; i += kBlock) tab[i] = coef[i];
+
+    Consts<T> c;
+    c.dx = T(a.dx);
+    c.dy = T(a.dy);
+    c.rdx = T(1.0 / a.dx);
+    c.rdy = T(1.0 / a.dy);
+    c.r2dx = T(0.5 / a.dx);
+    c.r2dy = T(0.5 / a.dy);
+    c.eps = T(a.eps);
+    c.cap = T(a.ros_cap);
+    c.visc_mode = a.visc_mode;
+    const T dt = T(a.dt);
+    const T t = T(a.t);
+    const T tp = T(a.t + a.dt);
+    const T INF = M<T>::inf();
+
+    // ---- load: psi everywhere in the frame, inputs where they are used
+    T p0[kRowsPerThread], uu[kRowsPerThread], vv[kRowsPerThread];
+    T zx[kRowsPerThread], zy[kRowsPerThread], told[kRowsPerThread], fold[kRowsPerThread];
+    T tig[kRowsPerThread];
+    int cc[kRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        const int gy = y0 - kHalo + fy;
+        const bool in = colin && fy < FH && gy >= 0 && gy < ny;
+        const bool r1 = in && xr1 && fy >= 1 && fy < a.tile_y + 5;
+        const bool r2 = in && xr2 && fy >= 2 && fy < a.tile_y + 4;
+        const bool r3 = in && xr3 && fy >= 3 && fy < a.tile_y + 3;
+        const size_t idx = in ? (size_t)gy * nx + gx : 0;
+        p0[k] = in ? psi_in[idx] : T(0);
+        uu[k] = r1 ? uw[idx] : T(0);
+        vv[k] = r1 ? vw[idx] : T(0);
+        zx[k] = r1 ? dzdx[idx] : T(0);
+        zy[k] = r1 ? dzdy[idx] : T(0);
+        const int cv = r1 ? (int)cat[idx] : 0;
+        cc[k] = cv < a.ncat ? cv : a.ncat - 1;   // the caller guarantees cv < ncat
+        told[k] = r2 ? tign[idx] : INF;
+        fold[k] = r3 ? frac[idx] : T(1);
+        tig[k] = INF;
+    }
+
+    // ---- step 1, ignition: psi := min(psi, psi_g); newly ignited nodes get
+    // the earliest arrival among the ignitions covering them (Sect. 4.4)
+    for (int g = 0; g < a.nign; g++) {
+        IgnGeo<T> geo;
+        if (!ign_setup<T>(a.ign[g], a.t, geo)) continue;
+        const double xg = ((double)gx + 0.5) * a.dx;
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; k++) {
+            const int fy = ty + kNR * k;
+            const double yg = ((double)(y0 - kHalo + fy) + 0.5) * a.dy;
+            T arr;
+            const T pg = ign_psi(geo, xg, yg, arr);
+            // earliest arrival among the ignitions covering the node; it
+            // counts below only where this step's ignition lit the node
+            if (pg <= T(0) && arr < tig[k]) tig[k] = arr;
+            if (pg < p0[k]) p0[k] = pg;
+        }
+    }
+    if (a.nign > 0) {
+        // tig holds the earliest covering arrival; it counts only where the
+        // ignition turned psi from > 0 to <= 0
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; k++) {
+            const int fy = ty + kNR * k;
+            const int gy = y0 - kHalo + fy;
+            const bool in = colin && fy < FH && gy >= 0 && gy < ny;
+            const size_t idx = in ? (size_t)gy * nx + gx : 0;
+            const T pold = in ? psi_in[idx] : T(0);
+            if (!(pold > T(0) && p0[k] <= T(0))) tig[k] = INF;
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        if (fy < FH) A[fy][tx] = p0[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        if (fy < FH) ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+    }
+    __syncthreads();
+
+    // ---- step 2a, first Heun stage on the tile plus two rings
+    T F1[kRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        const int gy = y0 - kHalo + fy;
+        const bool r1 = colin && xr1 && fy >= 1 && fy < a.tile_y + 5 && gy >= 0 && gy < ny;
+        F1[k] = T(0);
+        if (r1) {
+            F1[k] = rhs(A, fy, tx, uu[k], vv[k], zx[k], zy[k], tab + cc[k] * kNCoef, c);
+            B[fy][tx] = p0[k] + dt * F1[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        if (fy < FH) ghost_node(B, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+    }
+    __syncthreads();
+
+    // ---- step 2b, second stage on the tile plus one ring; step 3, ignition
+    // time of nodes crossed during the step (Eq. 14), first crossing kept
+    T p1[kRowsPerThread], tnew[kRowsPerThread], that[kRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        const int gy = y0 - kHalo + fy;
+        const bool r2 = colin && xr2 && fy >= 2 && fy < a.tile_y + 4 && gy >= 0 && gy < ny;
+        p1[k] = T(0);
+        tnew[k] = told[k];
+        that[k] = tp;
+        if (r2) {
+            const T F2 = rhs(B, fy, tx, uu[k], vv[k], zx[k], zy[k], tab + cc[k] * kNCoef, c);
+            const T pn = p0[k] + dt * (T(0.5) * F1[k] + T(0.5) * F2);
+            p1[k] = pn;
+            A[fy][tx] = pn;  // stage-1 reads of A finished at the last barrier
+            T ti = told[k];
+            if (is_inf(ti) && tig[k] < INF) ti = tig[k];
+            if (p0[k] > T(0) && pn <= T(0) && is_inf(ti)) ti = t + M<T>::div(p0[k] * dt, p0[k] - pn);
+            tnew[k] = ti;
+            that[k] = pn >= T(0) ? tp : ti;   // Eq. (17)
+        }
+    }
+    __syncthreads();
+    // node ignition times for the quadrature; ghost nodes get t' (reading
+    // R19), ghost psi is re-extrapolated including corners
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        if (fy < FH) {
+            B[fy][tx] = that[k];
+            ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, true);
+        }
+    }
+    __syncthreads();
+
+    // ---- steps 4-5: fuel fraction at t' (Eqs. 15-19) and cell fluxes
+    T fs[kRowsPerThread], fl[kRowsPerThread];
+    int st = 0;
+    const int gw = a.guard;
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        const int gy = y0 - kHalo + fy;
+        const bool r3 = colin && xr3 && fy >= 3 && fy < a.tile_y + 3 && gy >= 0 && gy < ny;
+        fs[k] = T(0);
+        fl[k] = T(0);
+        if (r3) {
+            const T *row = tab + cc[k] * kNCoef;
+            const T pc = A[fy][tx], tc = B[fy][tx];
+            T burned = T(0);
+#pragma unroll
+            for (int sb = -1; sb <= 1; sb += 2) {
+#pragma unroll
+                for (int sa = -1; sa <= 1; sa += 2) {
+                    const T pxe = A[fy][tx + sa], pye = A[fy + sb][tx], pxy = A[fy + sb][tx + sa];
+                    const T txe = B[fy][tx + sa], tye = B[fy + sb][tx], txy = B[fy + sb][tx + sa];
+                    T ps[4], ts[4];
+                    ps[0] = pc;
+                    ts[0] = tc;
+                    ps[1] = T(0.5) * (pc + pxe);
+                    ts[1] = T(0.5) * (tc + txe);
+                    ps[2] = T(0.5) * (pc + pye);
+                    ts[2] = T(0.5) * (tc + tye);
+                    ps[3] = T(0.25) * (pc + pxe + pye + pxy);
+                    ts[3] = T(0.25) * (tc + txe + tye + txy);
+                    T s = T(0), as = T(0), tau = T(0);
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        s += ps[q];
+                        as += tabs(ps[q]);
+                        tau += ps[q] >= T(0) ? T(0) : (tp - ts[q]);
+                    }
+                    const T beta = as > T(0) ? T(0.5) * (T(1) - M<T>::div(s, as)) : T(0);
+                    tau = M<T>::div(T(0.25) * tau, row[kTf]);
+                    burned += beta * M<T>::one_m_exp_neg(tau);
+                }
+            }
+            const T Fn = T(1) - T(0.25) * burned;
+            const T dF = M<T>::div(fold[k] - Fn, dt);
+            fs[k] = dF * row[kCh];
+            fl[k] = dF * row[kCq];
+            const size_t idx = (size_t)gy * nx + gx;
+            psi_out[idx] = p1[k];
+            frac[idx] = Fn;
+            if (!(tnew[k] == told[k])) tign[idx] = tnew[k];
+            const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
+            if (edge && p1[k] < T(0)) st |= kStBoundary;
+            if (!__builtin_isfinite(p1[k]) || !__builtin_isfinite(Fn)) st |= kStNonfinite;
+        }
+    }
+    if (st) atomicOr(status, st);
+    __syncthreads();
+
+    // ---- step 6: mean flux over each atmosphere cell of the tile
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; k++) {
+        const int fy = ty + kNR * k;
+        if (fy < FH) {
+            A[fy][tx] = fs[k];
+            B[fy][tx] = fl[k];
+        }
+    }
+    __syncthreads();
+    const int nI = a.tile_x / a.sr_x, nJ = a.tile_y / a.sr_y;
+    if (xr3) {
+        // column sums over the sr_y rows of each atmosphere row, written into
+        // the first row of the block (read before written, by this thread only)
+        for (int J = ty; J < nJ; J += kNR) {
+            const int r0 = kHalo + J * a.sr_y;
+            T s1 = T(0), s2 = T(0);
+            for (int r = 0; r < a.sr_y; r++) {
+                s1 += A[r0 + r][tx];
+                s2 += B[r0 + r][tx];
+            }
+            A[r0][tx] = s1;
+            B[r0][tx] = s2;
+        }
+    }
+    __syncthreads();
+    const int I0 = x0 / a.sr_x, J0 = y0 / a.sr_y;
+    for (int q = tid; q < nI * nJ; q += kBlock) {
+        const int J = q / nI, I = q - J * nI;
+        const int IG = I0 + I, JG = J0 + J;
+        if (IG >= a.nax || JG >= a.nay) continue;
+        const int cx0 = x0 + I * a.sr_x, cy0 = y0 + J * a.sr_y;
+        const int ncx = nx - cx0 < a.sr_x ? nx - cx0 : a.sr_x;
+        const int ncy = ny - cy0 < a.sr_y ? ny - cy0 : a.sr_y;
+        const int r0 = kHalo + J * a.sr_y, f0 = kHalo + I * a.sr_x;
+        T s1 = T(0), s2 = T(0);
+        for (int cI = 0; cI < a.sr_x; cI++) {
+            s1 += A[r0][f0 + cI];
+            s2 += B[r0][f0 + cI];
+        }
+        const T cnt = T(ncx * ncy);
+        fsens[(size_t)JG * a.nax + IG] = s1 / cnt;
+        flat[(size_t)JG * a.nax + IG] = s2 / cnt;
+    }
+}
+
+// ---------------------------------------------------------------- init kernels
+
+template <typename T>
+__global__ void k_fill(T *psi, T *tign, T *frac, size_t n, T psi0) {
+    const T INF = M<T>::inf();
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        psi[i] = psi0;
+        tign[i] = INF;
+        frac[i] = T(1);
+    }
+}
+
+// Per-category coefficients of Eq. (3) from the fuel data (Table 1) via the
+// Rothermel chain of Table 2 in English units, in double precision; plus
+// T_f (Eq. 4) and the flux factors of Eqs. (5)-(6).  One thread per category.
+template <typename T>
+__global__ void k_coef(const fire_fuel *fuels, int ncat, double wind_cap, T *coef) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncat) return;
+    const fire_fuel f = fuels[k];
+    constexpr double ft = 0.3048, lb = 0.45359237, btu = 1055.05585262;
+    constexpr double ftmin = ft / 60.0;  // m/s per ft/min
+    constexpr double Lw = 2.5e6;         // J/kg, latent heat (Sect. 2.3)
+    const double Mf = f.fuelmc_g;
+    double out[kNCoef];
+    out[kTf] = f.tf > 0.0 ? f.tf : f.weight * (-0.6 / ::log(0.6));
+    out[kCh] = f.fgi * f.cmbcnst / (1.0 + Mf);
+    out[kCq] = Lw * f.fgi * (Mf + 0.56) / (1.0 + Mf);
+    out[kM] = f.ros_mult;
+    if (f.ichap) {
+        // Eq. (2): S = min{6, max{0.03333, 1.2974 U}} in coefficient form
+        out[kS0] = 0.03333;
+        out[kR0] = 0.0;
+        out[kB] = 1.0;
+        out[kC] = 1.2974;
+        out[kD] = 0.0;
+        out[kE] = 6.0 / 1.2974;
+    } else {
+        // English units (lb, ft, min, BTU)
+        const double sig = f.savr * ft;
+        const double load = f.fgi * (ft * ft / lb) / (1.0 + Mf);     // w_0
+        const double rho_b = load / (f.fueldepthm / ft);
+        const double beta = rho_b / (f.fueldens * (ft * ft * ft / lb));
+        const double beta_op = 3.348 * ::pow(sig, -0.8189);
+        const double ratio = beta / beta_op;
+        const double Aexp = 1.0 / (4.77 * ::pow(sig, 0.1) - 7.27);
+        const double sig15 = ::pow(sig, 1.5);
+        const double gam = sig15 / (495.0 + 0.0594 * sig15) * ::pow(ratio, Aexp) *
+                           ::exp(Aexp * (1.0 - ratio));
+        double rm = Mf / f.fuelmce;
+        rm = rm < 1.0 ? rm : 1.0;
+        const double eta_m = 1.0 + rm * (-2.59 + rm * (5.11 - 3.52 * rm));
+        const double eta_s = 0.174 * ::pow(f.se, -0.19);
+        const double heat = f.cmbcnst * (lb / btu);
+        const double IR = gam * (load / (1.0 + f.st)) * heat * eta_m * eta_s;
+        const double xi = ::exp((0.792 + 0.681 * ::sqrt(sig)) * (beta + 0.1)) / (192.0 + 0.2595 * sig);
+        const double qig = 250.0 + 1116.0 * Mf;
+        const double R0 = IR * xi / (rho_b * ::exp(-138.0 / sig) * qig) * ftmin;   // m/s
+        const double Cw = 7.47 * ::exp(-0.133 * ::pow(sig, 0.55));
+        const double Bw = 0.02526 * ::pow(sig, 0.54);
+        const double Ew = 0.715 * ::exp(-3.59e-4 * sig);
+        out[kS0] = 0.0;
+        out[kR0] = R0;
+        out[kB] = Bw;
+        out[kC] = R0 * Cw * ::pow(ratio, -Ew) * ::pow(f.windrf / ftmin, Bw);
+        out[kD] = R0 * 5.275 * ::pow(beta, -0.3);
+        out[kE] = wind_cap;
+    }
+    for (int j = 0; j < kNCoef; j++) coef[k * kNCoef + j] = T(out[j]);
+}
+
+template <typename T>
+__global__ void k_ros_eval(const T *coef, int ncat, T cap, const uint8_t *cat, const T *un,
+                           const T *tn, T *S, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = cat[i] < ncat ? cat[i] : 0;
+        S[i] = ros(coef + k * kNCoef, un[i], tn[i], cap);
+    }
+}
+
+template <typename T> __global__ void k_to_f64(const T *src, double *dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
+
+template <typename T>
+hipError_t step_t(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
+    const size_t dyn = (size_t)a.ncat * kNCoef * sizeof(T);
+    const int grid = a.per_xcd * 8;
+    hipLaunchKernelGGL((k_step<T>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+                       (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
+                       (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
+                       b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(int dtype, const StepArgs &a, const StepBuffers &b, hipStream_t s) {
+    return dtype == FIRE_F64 ? step_t<double>(a, b, s) : step_t<float>(a, b, s);
+}
+
+hipError_t launch_coef(int dtype, const fire_fuel *fuels_dev, int ncat, double wind_cap,
+                       void *coef_dev, hipStream_t s) {
+    const int blk = 64, grid = (ncat + blk - 1) / blk;
+    if (dtype == FIRE_F64)
+        hipLaunchKernelGGL((k_coef<double>), dim3(grid), dim3(blk), 0, s, fuels_dev, ncat,
+                           wind_cap, (double *)coef_dev);
+    else
+        hipLaunchKernelGGL((k_coef<float>), dim3(grid), dim3(blk), 0, s, fuels_dev, ncat,
+                           wind_cap, (float *)coef_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int dtype, void *psi, void *tign, void *frac, size_t n, double psi0,
+                       hipStream_t s) {
+    const int blk = 256;
+    size_t g = (n + blk - 1) / blk;
+    const int grid = (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+    if (dtype == FIRE_F64)
+        hipLaunchKernelGGL((k_fill<double>), dim3(grid), dim3(blk), 0, s, (double *)psi,
+                           (double *)tign, (double *)frac, n, psi0);
+    else
+        hipLaunchKernelGGL((k_fill<float>), dim3(grid), dim3(blk), 0, s, (float *)psi,
+                           (float *)tign, (float *)frac, n, (float)psi0);
+    return hipGetLastError();
+}
+
+hipError_t launch_ros_eval(int dtype, const void *coef, int ncat, double ros_cap,
+                           const uint8_t *cat, const void *un, const void *tn, void *S,
+                           int64_t n, hipStream_t s) {
+    const int blk = 256;
+    int64_t g = (n + blk - 1) / blk;
+    const int grid = (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+    if (dtype == FIRE_F64)
+        hipLaunchKernelGGL((k_ros_eval<double>), dim3(grid), dim3(blk), 0, s,
+                           (const double *)coef, ncat, ros_cap, cat, (const double *)un,
+                           (const double *)tn, (double *)S, n);
+    else
+        hipLaunchKernelGGL((k_ros_eval<float>), dim3(grid), dim3(blk), 0, s,
+                           (const float *)coef, ncat, (float)ros_cap, cat, (const float *)un,
+                           (const float *)tn, (float *)S, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_to_f64(int dtype, const void *coef, double *out, int n, hipStream_t s) {
+    const int blk = 256, grid = (n + blk - 1) / blk;
+    if (dtype == FIRE_F64)
+        hipLaunchKernelGGL((k_to_f64<double>), dim3(grid), dim3(blk), 0, s, (const double *)coef,
+                           out, n);
+    else
+        hipLaunchKernelGGL((k_to_f64<float>), dim3(grid), dim3(blk), 0, s, (const float *)coef,
+                           out, n);
+    return hipGetLastError();
+}
+
+}  // namespace fire

@@ -1,0 +1,293 @@
+"""Python binding of the HIP fire-step library (``libfire_gfx950.so``).
+
+Argument marshalling only: torch tensors provide device memory and the
+stream; every step of the method runs in the library's HIP kernels.  The
+names follow the C ABI in ``include/fire.h``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfire_gfx950.so")
+
+FIRE_F32, FIRE_F64 = 0, 1
+STATUS_BOUNDARY, STATUS_NONFINITE = 1, 2
+ERR_BOUNDARY = -4
+MAX_IGNITIONS = 8
+NCOEF = 10
+COEF_NAMES = ("S0", "R0", "b", "c", "d", "e", "m", "Tf", "Ch", "Cq")
+
+
+class FireError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class fire_mesh(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("sr_x", C.c_int32), ("sr_y", C.c_int32), ("dtype", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class fire_fuel(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "windrf", "tf", "weight", "fgi", "fueldepthm", "savr", "fuelmce", "fueldens", "st",
+        "se", "cmbcnst", "fuelmc_g", "ros_mult")] + [("ichap", C.c_int32), ("reserved", C.c_int32)]
+
+
+class fire_ignition(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "ax", "ay", "bx", "by", "t_start", "radius", "ros", "vx", "vy", "t_end")]
+
+
+class fire_params(C.Structure):
+    _fields_ = [("viscosity", C.c_double), ("psi_init", C.c_double), ("wind_cap", C.c_double),
+                ("ros_cap", C.c_double), ("t0", C.c_double), ("guard_width", C.c_int32),
+                ("boundary_policy", C.c_int32), ("viscosity_mode", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class fire_view(C.Structure):
+    _fields_ = [("psi", C.c_void_p), ("tign", C.c_void_p), ("frac", C.c_void_p),
+                ("t", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP fire library not built: {LIB_PATH} missing "
+                               "(run paper_1102_1343_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.fire_state_bytes.argtypes = [P(fire_mesh), C.c_int32]
+        L.fire_state_bytes.restype = C.c_size_t
+        L.fire_init.argtypes = [P(vp), P(fire_mesh), P(fire_fuel), C.c_int32, vp, vp, vp,
+                                P(fire_ignition), C.c_int32, P(fire_params), vp, C.c_size_t, vp]
+        L.fire_step.argtypes = [vp, vp, vp, C.c_double, vp, vp, P(fire_view)]
+        L.fire_get_state.argtypes = [vp, P(fire_view)]
+        L.fire_set_state.argtypes = [vp, vp, vp, vp, C.c_double]
+        L.fire_status.argtypes = [vp]
+        L.fire_coef.argtypes = [vp, P(C.c_double), C.c_int32]
+        L.fire_ros_eval.argtypes = [vp, vp, vp, vp, vp, C.c_int64]
+        L.fire_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
+        L.fire_get_tile.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+        L.fire_set_stream.argtypes = [vp, vp]
+        L.fire_strerror.argtypes = [C.c_int]
+        L.fire_strerror.restype = C.c_char_p
+        L.fire_destroy.argtypes = [vp]
+        L.fire_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().fire_strerror(int(code)).decode()
+
+
+def _check(code, what):
+    if code != 0:
+        raise FireError(code, what)
+
+
+def _fuel_array(fuels):
+    arr = (fire_fuel * len(fuels))()
+    for k, f in enumerate(fuels):
+        for name, typ in fire_fuel._fields_:
+            if name != "reserved":
+                setattr(arr[k], name, typ(f[name]))
+    return arr
+
+
+def _ign_array(igns):
+    arr = (fire_ignition * max(1, len(igns)))()
+    for k, g in enumerate(igns):
+        for name, _ in fire_ignition._fields_:
+            setattr(arr[k], name, float(g[name]))
+    return arr
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Fire:
+    """One fire domain on one GPU, driven through the C ABI.
+
+    ``fuels`` are dicts with the ``fire_fuel`` field names, ``cat`` a uint8
+    [ny, nx] category map, ``dzdx``/``dzdy`` the terrain gradient,
+    ``ignitions`` dicts with the ``fire_ignition`` field names.  Host arrays
+    are copied to the device once; device tensors are used in place.
+    """
+
+    def __init__(self, nx, ny, dx, dy, sr_x, sr_y, fuels, cat, dzdx, dzdy, ignitions=(),
+                 dtype=torch.float32, device="cuda", viscosity=0.4, psi_init=0.0, wind_cap=30.0,
+                 ros_cap=math.inf, t0=0.0, guard_width=1, boundary_policy=0, viscosity_mode=0,
+                 stream=None):
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        if len(ignitions) > MAX_IGNITIONS:
+            raise ValueError(f"at most {MAX_IGNITIONS} ignitions")
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.nx, self.ny = int(nx), int(ny)
+        self.nax = -(-self.nx // int(sr_x))
+        self.nay = -(-self.ny // int(sr_y))
+        self.mesh = fire_mesh(self.nx, self.ny, float(dx), float(dy), int(sr_x), int(sr_y),
+                              FIRE_F64 if dtype == torch.float64 else FIRE_F32, 0)
+        self.ncat = len(fuels)
+        self.cat = self._dev(cat, torch.uint8)
+        if int(self.cat.max()) >= self.ncat:
+            raise ValueError("fuel category map holds a value >= number of fuels")
+        self.dzdx = self._dev(dzdx, dtype)
+        self.dzdy = self._dev(dzdy, dtype)
+        self.params = fire_params(float(viscosity), float(psi_init), float(wind_cap),
+                                  float(ros_cap), float(t0), int(guard_width),
+                                  int(boundary_policy), int(viscosity_mode), 0)
+        nbytes = lib().fire_state_bytes(C.byref(self.mesh), self.ncat)
+        if nbytes == 0:
+            raise FireError(-1, "fire_state_bytes")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        pad = (-self.arena.data_ptr()) % 256
+        self._base = self.arena.data_ptr() + pad
+        self._stream = stream
+        fuels_c = _fuel_array(fuels)
+        ign_c = _ign_array(list(ignitions))
+        ctx = C.c_void_p()
+        _check(lib().fire_init(C.byref(ctx), C.byref(self.mesh), fuels_c, self.ncat,
+                               C.c_void_p(self.cat.data_ptr()), C.c_void_p(self.dzdx.data_ptr()),
+                               C.c_void_p(self.dzdy.data_ptr()), ign_c, len(ignitions),
+                               C.byref(self.params), C.c_void_p(self._base), nbytes,
+                               _stream_handle(stream)), "fire_init")
+        self._ctx = ctx
+        self._pad = pad
+
+    @classmethod
+    def from_problem(cls, prob, dtype=torch.float32, device="cuda", **kw):
+        """Build from a ``synth.Problem`` (same inputs the oracle takes)."""
+        p = dict(prob.params)
+        p.update(kw)
+        return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.sr_x, prob.sr_y, prob.fuels,
+                   prob.cat, prob.dzdx, prob.dzdy, prob.ignitions, dtype=dtype, device=device,
+                   **{k: v for k, v in p.items() if k in (
+                       "viscosity", "psi_init", "wind_cap", "ros_cap", "t0", "guard_width",
+                       "boundary_policy", "viscosity_mode", "stream")})
+
+    def _dev(self, a, dtype):
+        if isinstance(a, torch.Tensor):
+            t = a.to(device=self.device, dtype=dtype)
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(a)).to(device=self.device, dtype=dtype)
+        t = t.contiguous()
+        if tuple(t.shape) != (self.ny, self.nx):
+            raise ValueError(f"expected shape {(self.ny, self.nx)}, got {tuple(t.shape)}")
+        return t
+
+    # ------------------------------------------------------------ calls
+    def new_flux(self):
+        z = lambda: torch.empty((self.nay, self.nax), dtype=self.dtype, device=self.device)
+        return z(), z()
+
+    def step(self, u, v, dt, flux_sens=None, flux_lat=None, check=True):
+        """One fire step; returns (flux_sens, flux_lat) on the atmosphere mesh.
+        Raises FireError on an error code (FIRE_ERR_BOUNDARY under the stop
+        policy) unless ``check`` is False, in which case the code is returned
+        as the third element."""
+        if flux_sens is None or flux_lat is None:
+            flux_sens, flux_lat = self.new_flux()
+        for t in (u, v):
+            if t.dtype != self.dtype or not t.is_contiguous() or t.shape != (self.ny, self.nx):
+                raise ValueError("wind must be contiguous [ny, nx] tensors of the fire dtype")
+        rc = lib().fire_step(self._ctx, C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
+                             float(dt), C.c_void_p(flux_sens.data_ptr()),
+                             C.c_void_p(flux_lat.data_ptr()), None)
+        if check:
+            _check(rc, "fire_step")
+            return flux_sens, flux_lat
+        return flux_sens, flux_lat, rc
+
+    def _view(self):
+        vw = fire_view()
+        _check(lib().fire_get_state(self._ctx, C.byref(vw)), "fire_get_state")
+        return vw
+
+    def _slice(self, ptr):
+        off = ptr - self.arena.data_ptr()
+        es = 8 if self.dtype == torch.float64 else 4
+        n = self.nx * self.ny
+        return self.arena[off:off + n * es].view(self.dtype).view(self.ny, self.nx)
+
+    @property
+    def psi(self):
+        return self._slice(self._view().psi)
+
+    @property
+    def tign(self):
+        return self._slice(self._view().tign)
+
+    @property
+    def frac(self):
+        return self._slice(self._view().frac)
+
+    @property
+    def t(self):
+        return self._view().t
+
+    def set_state(self, psi, tign, frac, t):
+        psi, tign, frac = (self._dev(a, self.dtype) for a in (psi, tign, frac))
+        _check(lib().fire_set_state(self._ctx, C.c_void_p(psi.data_ptr()),
+                                    C.c_void_p(tign.data_ptr()), C.c_void_p(frac.data_ptr()),
+                                    float(t)), "fire_set_state")
+        (self._stream or torch.cuda.current_stream()).synchronize()
+
+    def status(self) -> int:
+        rc = lib().fire_status(self._ctx)
+        if rc < 0:
+            raise FireError(rc, "fire_status")
+        return rc
+
+    def coef(self) -> np.ndarray:
+        out = np.zeros((self.ncat, NCOEF))
+        _check(lib().fire_coef(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)), self.ncat),
+               "fire_coef")
+        return out
+
+    def ros_eval(self, cat, un, tn):
+        S = torch.empty_like(un)
+        _check(lib().fire_ros_eval(self._ctx, C.c_void_p(cat.data_ptr()),
+                                   C.c_void_p(un.data_ptr()), C.c_void_p(tn.data_ptr()),
+                                   C.c_void_p(S.data_ptr()), un.numel()), "fire_ros_eval")
+        return S
+
+    def set_tile(self, tile_x, tile_y):
+        _check(lib().fire_set_tile(self._ctx, int(tile_x), int(tile_y)), "fire_set_tile")
+
+    def get_tile(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().fire_get_tile(self._ctx, C.byref(a), C.byref(b)), "fire_get_tile")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().fire_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -65,7 +65,8 @@ def ignition(ax, ay, bx=None, by=None, t_start=0.0, radius=0.0, ros=math.inf,
 
 @dataclass
 class Problem:
-    """Everything one fire run needs, in float64 host arrays."""
+    """Everything one fire run needs, as host arrays (float64, or float32 for
+    the large single-precision workloads)."""
     nx: int
     ny: int
     dx: float
@@ -74,12 +75,12 @@ class Problem:
     sr_y: int
     fuels: list
     cat: np.ndarray            # uint8 [ny, nx]
-    dzdx: np.ndarray           # float64 [ny, nx]
+    dzdx: np.ndarray           # [ny, nx]
     dzdy: np.ndarray
     ignitions: list
     dt: float
     steps: int
-    wind: list                 # list of (u, v) float64 [ny, nx] fields
+    wind: list                 # list of (u, v) [ny, nx] fields
     wind_period: int = 0       # steps per wind field (0: one field for all)
     params: dict = field(default_factory=dict)
     name: str = ""
@@ -126,14 +127,14 @@ def voronoi_categories(rng, nx, ny, nsites=256, ncat=13) -> np.ndarray:
     return out
 
 
-def hills_gradient(rng, nx, ny, dx, dy, nhills=8, max_slope=0.30):
+def hills_gradient(rng, nx, ny, dx, dy, nhills=8, max_slope=0.30, dtype=np.float64):
     """Analytic gradient of a sum of Gaussian hills z = sum_h A_h exp(-r^2/(2 s_h^2)).
 
     Centres uniform in the domain, widths s_h uniform in [0.04, 0.15] L, peak
     slopes g_h uniform in [0.05, 0.30] with A_h = g_h s_h e^(1/2) (the peak
     slope of one hill).  The summed gradient is rescaled so its largest norm
     is at most ``max_slope``.  Each hill is separable, so the fields are
-    built as rank-``nhills`` products.
+    built as rank-``nhills`` products (in ``dtype``).
     """
     L = max(nx * dx, ny * dy)
     x = (np.arange(nx) + 0.5) * dx
@@ -147,17 +148,18 @@ def hills_gradient(rng, nx, ny, dx, dy, nhills=8, max_slope=0.30):
     ey = np.exp(-((y[None, :] - cy[:, None]) ** 2) / (2 * s[:, None] ** 2))      # [h, ny]
     fx = -(A / s ** 2)[:, None] * (x[None, :] - cx[:, None]) * ex                  # d/dx factor
     fy = -(A / s ** 2)[:, None] * (y[None, :] - cy[:, None]) * ey
-    dzdx = ey.T @ fx            # [ny, nx]
-    dzdy = fy.T @ ex
-    nrm = np.sqrt(dzdx ** 2 + dzdy ** 2).max()
+    c = lambda a: np.ascontiguousarray(a, dtype=dtype)
+    dzdx = c(ey.T) @ c(fx)            # [ny, nx]
+    dzdy = c(fy.T) @ c(ex)
+    nrm = float(np.sqrt(np.max(dzdx * dzdx + dzdy * dzdy)))
     if nrm > max_slope:
-        dzdx *= max_slope / nrm
-        dzdy *= max_slope / nrm
-    return np.ascontiguousarray(dzdx), np.ascontiguousarray(dzdy)
+        dzdx *= dtype(max_slope / nrm)
+        dzdy *= dtype(max_slope / nrm)
+    return dzdx, dzdy
 
 
 def fourier_wind(rng, nx, ny, dx, dy, nmodes=16, mean_speed=4.0, max_speed=8.0,
-                 amp_scale=1.0, rotate_deg=0.0):
+                 amp_scale=1.0, rotate_deg=0.0, dtype=np.float64):
     """Smooth surface wind: a mean wind (direction uniform, ``mean_speed``) plus
     ``nmodes`` Fourier modes alpha_m cos(2 pi k_m.x / L + phi_m) with integer
     wave vectors k_m in [-4,4]^2 minus 0 and independent amplitudes for u and
@@ -179,17 +181,24 @@ def fourier_wind(rng, nx, ny, dx, dy, nmodes=16, mean_speed=4.0, max_speed=8.0,
     av = rng.normal(0.0, 1.0, nmodes)
     ax_ = 2 * math.pi * k[:, 0][None, :] * x[:, None] / Lx + phi[None, :]   # [nx, m]
     by_ = 2 * math.pi * k[:, 1][None, :] * y[:, None] / Ly                  # [ny, m]
-    X = np.concatenate([np.cos(ax_), np.sin(ax_)], axis=1)                 # [nx, 2m]
-    Yu = np.concatenate([au * np.cos(by_), -au * np.sin(by_)], axis=1)      # [ny, 2m]
-    Yv = np.concatenate([av * np.cos(by_), -av * np.sin(by_)], axis=1)
-    u = mean_speed * math.cos(th) + Yu @ X.T
-    v = mean_speed * math.sin(th) + Yv @ X.T
-    sp = np.sqrt(u ** 2 + v ** 2).max()
+    c = lambda a: np.ascontiguousarray(a, dtype=dtype)
+    X = c(np.concatenate([np.cos(ax_), np.sin(ax_)], axis=1).T)            # [2m, nx]
+    Yu = c(np.concatenate([au * np.cos(by_), -au * np.sin(by_)], axis=1))   # [ny, 2m]
+    Yv = c(np.concatenate([av * np.cos(by_), -av * np.sin(by_)], axis=1))
+    u = Yu @ X
+    u += dtype(mean_speed * math.cos(th))
+    v = Yv @ X
+    v += dtype(mean_speed * math.sin(th))
+    sp = float(np.sqrt(np.max(u * u + v * v)))
     sc = max_speed / sp * amp_scale
-    c, s_ = math.cos(math.radians(rotate_deg)), math.sin(math.radians(rotate_deg))
-    ur = sc * (c * u - s_ * v)
-    vr = sc * (s_ * u + c * v)
-    return np.ascontiguousarray(ur), np.ascontiguousarray(vr)
+    cr, sr = math.cos(math.radians(rotate_deg)), math.sin(math.radians(rotate_deg))
+    if rotate_deg == 0.0:
+        u *= dtype(sc)
+        v *= dtype(sc)
+        return u, v
+    ur = dtype(sc * cr) * u - dtype(sc * sr) * v
+    vr = dtype(sc * sr) * u + dtype(sc * cr) * v
+    return ur, vr
 
 
 def random_fuels(rng, ncat=13) -> list:
@@ -255,23 +264,40 @@ def uniform_fire(n=128, dx=6.0, steps=200, dt=0.5, wind=(2.0, 0.0)) -> Problem:
 
 
 def patchy_fire(n=2048, dx=6.0, steps=2000, dt=0.25, nwind=1, wind_period=0,
-                seed=SEED) -> Problem:
+                seed=SEED, field_dtype=np.float64) -> Problem:
     """FP32 production workload: n x n mesh, dx = 6 m, 13 fuel categories as
     256 seeded Voronoi patches with random parameters, 8 Gaussian hills (slopes
     up to 30 %), a 16-mode Fourier wind (0-8 m/s), 4 seeded line ignitions,
     dt = 0.25 s, refinement 10, spread rate capped at 6 m/s.  With ``nwind`` > 1
     several wind fields are drawn and cycled every ``wind_period`` steps
-    (time-varying coupling input)."""
+    (time-varying coupling input).  ``field_dtype`` is the precision the
+    dense fields are synthesised in (float32 for the large FP32 workloads)."""
     rng = np.random.default_rng(seed)
     fuels = random_fuels(rng)
     cat = voronoi_categories(rng, n, n)
-    gzx, gzy = hills_gradient(rng, n, n, dx, dx)
+    gzx, gzy = hills_gradient(rng, n, n, dx, dx, dtype=field_dtype)
     ign = line_ignitions(rng, n, n, dx, dx)
     winds = []
     for w in range(max(1, nwind)):
         wr = np.random.default_rng([seed, 1000 + w])
-        winds.append(fourier_wind(wr, n, n, dx, dx))
+        winds.append(fourier_wind(wr, n, n, dx, dx, dtype=field_dtype))
     return Problem(n, n, dx, dx, 10, 10, fuels, cat, gzx, gzy, ign, dt, steps, winds,
                    wind_period, dict(viscosity=0.4, viscosity_mode=0, ros_cap=6.0,
                                      boundary_policy=1, guard_width=1),
                    name=f"patchy{n}")
+
+
+def window(prob: Problem, i0: int, j0: int, w: int, h: int) -> Problem:
+    """The sub-mesh [j0:j0+h, i0:i0+w] of ``prob`` as a problem of its own:
+    arrays sliced, ignition coordinates shifted to the window origin.  With
+    i0, j0 multiples of the refinement ratio its atmosphere cells are cells
+    of the full mesh."""
+    sl = (slice(j0, j0 + h), slice(i0, i0 + w))
+    ox, oy = i0 * prob.dx, j0 * prob.dy
+    c = lambda a: np.ascontiguousarray(a[sl])
+    ign = [dict(g, ax=g["ax"] - ox, ay=g["ay"] - oy, bx=g["bx"] - ox, by=g["by"] - oy)
+           for g in prob.ignitions]
+    return Problem(w, h, prob.dx, prob.dy, prob.sr_x, prob.sr_y, [dict(f) for f in prob.fuels],
+                   c(prob.cat), c(prob.dzdx), c(prob.dzdy), ign, prob.dt, prob.steps,
+                   [(c(u), c(v)) for (u, v) in prob.wind], prob.wind_period, dict(prob.params),
+                   f"{prob.name}[{j0}:{j0 + h},{i0}:{i0 + w}]")

@@ -1,0 +1,78 @@
+"""The C ABI library loads on a machine without a GPU, exports every symbol
+that include/fire.h declares, agrees with the header on struct layouts, and
+rejects bad arguments before touching the device.  CPU only."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fire.h")
+LIB = os.path.join(ROOT, "paper_1102_1343_amd", "libfire_gfx950.so")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fire_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    return C.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_1102_1343_amd import fire as F
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include "fire.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fire_mesh),'
+                    'sizeof(fire_fuel), sizeof(fire_ignition), sizeof(fire_params),'
+                    'sizeof(fire_view), offsetof(fire_params, guard_width));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [C.sizeof(F.fire_mesh), C.sizeof(F.fire_fuel), C.sizeof(F.fire_ignition),
+            C.sizeof(F.fire_params), C.sizeof(F.fire_view), F.fire_params.guard_width.offset]
+    assert got == want
+
+
+def test_state_bytes_and_errors_without_gpu(lib):
+    from paper_1102_1343_amd import fire as F
+    lib.fire_state_bytes.restype = C.c_size_t
+    lib.fire_strerror.restype = C.c_char_p
+    m = F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, F.FIRE_F32, 0)
+    n = 128 * 96
+    nb = lib.fire_state_bytes(C.byref(m), 13)
+    # psi x2, t_i, F (4 B each) plus the table, fuel staging and status word
+    assert 16 * n <= nb <= 16 * n + 8 * 256 + 13 * (10 * 4 + 112) + 256
+    m64 = F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, F.FIRE_F64, 0)
+    assert lib.fire_state_bytes(C.byref(m64), 13) >= 32 * n
+    for bad in (F.fire_mesh(1, 96, 6.0, 6.0, 10, 10, 0, 0), F.fire_mesh(128, 96, 0.0, 6.0, 10, 10, 0, 0),
+                F.fire_mesh(128, 96, 6.0, 6.0, 0, 10, 0, 0), F.fire_mesh(128, 96, 6.0, 6.0, 10, 27, 0, 0),
+                F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, 7, 0)):
+        assert lib.fire_state_bytes(C.byref(bad), 13) == 0
+    assert lib.fire_state_bytes(C.byref(m), 0) == 0
+    assert lib.fire_state_bytes(C.byref(m), 257) == 0
+    assert lib.fire_abi_version() == 1
+    assert lib.fire_strerror(-4) == b"fire reached the domain boundary guard ring"
+    assert lib.fire_strerror(0) == b"ok"
+    # argument errors are reported before any device work
+    ctx = C.c_void_p()
+    assert lib.fire_init(C.byref(ctx), None, None, 0, None, None, None, None, 0, None, None,
+                         C.c_size_t(0), None) == -1
+    assert lib.fire_step(None, None, None, C.c_double(0.5), None, None, None) == -1
+    assert lib.fire_status(None) == -1

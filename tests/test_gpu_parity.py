@@ -1,0 +1,257 @@
+"""HIP path vs oracle, element by element, through the C ABI (needs a GPU).
+
+Workloads: the uniform FP64 case (128 x 128, one fuel, 2 m/s wind, one
+instant circular ignition, 200 steps) and the patchy generator (13 Voronoi
+fuels, Gaussian hills, Fourier wind, 4 line ignitions) at sizes the oracle
+finishes in seconds, plus ragged and tiny meshes, other refinement ratios,
+drip torches, the literal viscosity form, tile-shape invariance,
+determinism, checkpoint/resume and the status word."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1102_1343_amd import fire as F
+from paper_1102_1343_amd import synth
+
+from parity import Compare64, front_error, gpu_fire, host, total_flux, wind_tensors
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def run_fp64(prob, steps, tile=None, **kw):
+    _log(f"fp64 parity {prob.name} {prob.nx}x{prob.ny} steps={steps} tile={tile}")
+    g = gpu_fire(prob, torch.float64, tile=tile, **kw)
+    o = oracle.OracleFire(prob, **{k: v for k, v in kw.items()
+                                   if k in ("viscosity", "viscosity_mode", "ros_cap", "guard_width")})
+    W = wind_tensors(prob, torch.float64)
+    cmp = Compare64(prob)
+    fs, fl = g.new_flux()
+    for k in range(steps):
+        wi = 0 if prob.wind_period <= 0 else (k // prob.wind_period) % len(W)
+        prev, t_prev = o.psi.copy(), o.t
+        g.step(W[wi][0], W[wi][1], prob.dt, fs, fl)
+        fs_o, fl_o = o.step(*prob.wind_at(k), prob.dt)
+        torch.cuda.synchronize()
+        cmp.step(g, o, fs, fl, fs_o, fl_o, prev, t_prev)
+    assert cmp.knife_cells <= 1e-4 * cmp.cells + 2
+    return g, o
+
+
+def test_coefficients_match_oracle():
+    rng = np.random.default_rng(21)
+    fuels = synth.random_fuels(rng, 13) + [synth.fuel(ichap=1), synth.fuel(tf=0.0, weight=500.0),
+                                            synth.fuel(fuelmc_g=0.3, fuelmce=0.3)]
+    prob = synth.uniform_fire(16)
+    prob.fuels = fuels
+    ref = oracle.coef(fuels)
+    for dt, rel in ((torch.float64, 1e-13), (torch.float32, 1e-6)):
+        g = gpu_fire(prob, dt)
+        got = g.coef()
+        assert np.allclose(got, ref, rtol=rel, atol=1e-15 if dt == torch.float64 else 1e-9)
+
+
+def test_ros_eval_matches_oracle():
+    rng = np.random.default_rng(22)
+    fuels = synth.random_fuels(rng, 12) + [synth.fuel(ichap=1)]
+    prob = synth.uniform_fire(16)
+    prob.fuels = fuels
+    n = 20000
+    cat = rng.integers(0, 13, n).astype(np.uint8)
+    un = rng.uniform(-10, 40, n)
+    tn = rng.uniform(-0.5, 0.8, n)
+    tab = oracle.coef(fuels)
+    ref = np.array([oracle.ros(tab[c], a, b, 6.0) for c, a, b in zip(cat, un, tn)])
+    for dt, rel in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        g = gpu_fire(prob, dt, ros_cap=6.0)
+        S = g.ros_eval(torch.from_numpy(cat).cuda(), torch.from_numpy(un).to("cuda", dt),
+                       torch.from_numpy(tn).to("cuda", dt))
+        got = host(S)
+        if dt == torch.float32:
+            # inputs rounded to float first
+            un32 = un.astype(np.float32).astype(np.float64)
+            tn32 = tn.astype(np.float32).astype(np.float64)
+            ref = np.array([oracle.ros(tab[c], a, b, 6.0) for c, a, b in zip(cat, un32, tn32)])
+        assert np.allclose(got, ref, rtol=rel, atol=1e-12)
+
+
+def test_uniform_fire_fp64_full_run():
+    prob = synth.uniform_fire(128)
+    g, o = run_fp64(prob, prob.steps)
+    assert (o.frac < 1).sum() > 10 and np.isfinite(o.tign).sum() > 10
+
+
+def test_patchy_fp64():
+    prob = synth.patchy_fire(n=240, steps=240)
+    g, o = run_fp64(prob, prob.steps)
+    assert np.isfinite(o.tign).sum() > 100
+
+
+def test_patchy_fp64_other_tiles_and_wind_changes():
+    prob = synth.patchy_fire(n=200, steps=120, nwind=3, wind_period=10)
+    run_fp64(prob, prob.steps, tile=(60, 10))
+
+
+@pytest.mark.parametrize("shape,sr", [((137, 91), (10, 10)), ((64, 50), (7, 3)), ((33, 129), (1, 1)),
+                                      ((2, 2), (1, 1)), ((5, 3), (2, 2)), ((3, 40), (4, 5))])
+def test_ragged_and_tiny_meshes_fp64(shape, sr):
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 1000 + ny)
+    fuels = synth.random_fuels(rng, 3)
+    cat = rng.integers(0, 3, (ny, nx)).astype(np.uint8)
+    gzx = rng.uniform(-0.1, 0.3, (ny, nx))
+    gzy = rng.uniform(-0.1, 0.3, (ny, nx))
+    u = rng.uniform(-2, 6, (ny, nx))
+    v = rng.uniform(-2, 6, (ny, nx))
+    dx, dy = 6.0, 4.0
+    ign = [synth.ignition(nx * dx * 0.4, ny * dy * 0.5, nx * dx * 0.6, ny * dy * 0.55,
+                          t_start=0.0, radius=8.0, ros=0.5)]
+    prob = synth.Problem(nx, ny, dx, dy, sr[0], sr[1], fuels, cat, gzx, gzy, ign, 0.25, 60,
+                         [(u, v)], 0, dict(viscosity=0.4, viscosity_mode=0, ros_cap=6.0,
+                                           boundary_policy=1, guard_width=1), name="ragged")
+    run_fp64(prob, prob.steps)
+
+
+def test_drip_torch_and_literal_viscosity_fp64():
+    prob = synth.patchy_fire(n=160, steps=100)
+    c = 80 * 6.0
+    prob.ignitions = [synth.ignition(c - 100, c, t_start=0.5, radius=9.0, ros=0.4, vx=3.0, vy=1.0,
+                                     t_end=15.0),
+                      synth.ignition(c + 60, c - 60, t_start=0.0, radius=10.0),
+                      # end points off the cell-centre lattice: a segment through
+                      # cell centres puts psi_g = 0 exactly on nodes at t = t_g,
+                      # where rounding alone decides the ignition
+                      synth.ignition(c + 50.37, c + 70.11, c + 90.83, c + 29.57, t_start=2.0,
+                                     radius=6.0, ros=0.7)]
+    run_fp64(prob, prob.steps)
+    prob.params["viscosity_mode"] = 1
+    prob.params["viscosity"] = 0.05
+    run_fp64(prob, 60, viscosity_mode=1, viscosity=0.05)
+
+
+def test_patchy_fp32_front_and_flux():
+    prob = synth.patchy_fire(n=256, steps=400)
+    p32 = prob.cast(np.float32)
+    _log("fp32 parity patchy256 400 steps")
+    g = gpu_fire(prob, torch.float32)
+    o = oracle.OracleFire(p32)
+    W = wind_tensors(prob, torch.float32)
+    fs, fl = g.new_flux()
+    tot_g, tot_o, worst = [], [], 0.0
+    for k in range(prob.steps):
+        g.step(W[0][0], W[0][1], prob.dt, fs, fl)
+        fs_o, fl_o = o.step(*p32.wind[0], prob.dt)
+        tot_g.append((total_flux(host(fs), prob), total_flux(host(fl), prob)))
+        tot_o.append((total_flux(fs_o, prob), total_flux(fl_o, prob)))
+        if k % 20 == 19:
+            worst = max(worst, front_error(host(g.psi), o.psi, prob.dx, prob.dy))
+    assert worst <= 0.05, worst
+    tg, to = np.array(tot_g), np.array(tot_o)
+    for j in range(2):
+        peak = np.max(np.abs(to[:, j]))
+        big = np.abs(to[:, j]) > 1e-3 * peak
+        assert big.sum() > 50
+        rel = np.abs(tg[big, j] - to[big, j]) / np.abs(to[big, j])
+        assert rel.max() <= 1e-4, rel.max()
+        assert abs(tg[:, j].sum() - to[:, j].sum()) <= 1e-4 * abs(to[:, j].sum())
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_tile_shape_invariance_and_determinism(dtype):
+    """Results are bitwise the same for every tile shape and every run: a
+    detector for halo and race mistakes."""
+    prob = synth.patchy_fire(n=300, steps=80)
+    W = wind_tensors(prob, dtype)
+    outs = []
+    for tile in (None, (120, 20), (60, 10), (10, 10), (110, 20), (20, 10), None):
+        g = gpu_fire(prob, dtype, tile=tile)
+        fs, fl = g.new_flux()
+        acc = torch.zeros_like(fs)
+        for _ in range(prob.steps):
+            g.step(W[0][0], W[0][1], prob.dt, fs, fl)
+            acc += fs
+        torch.cuda.synchronize()
+        outs.append((host(g.psi), host(g.tign), host(g.frac), host(acc), host(fl)))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b, equal_nan=True)
+
+
+def test_checkpoint_resume_bitwise():
+    prob = synth.patchy_fire(n=200, steps=60)
+    W = wind_tensors(prob, torch.float32)
+    a = gpu_fire(prob, torch.float32)
+    for _ in range(30):
+        a.step(W[0][0], W[0][1], prob.dt)
+    ck = (a.psi.clone(), a.tign.clone(), a.frac.clone(), a.t)
+    for _ in range(30):
+        a.step(W[0][0], W[0][1], prob.dt)
+    b = gpu_fire(prob, torch.float32)
+    b.set_state(*ck)
+    assert b.t == ck[3]
+    for _ in range(30):
+        b.step(W[0][0], W[0][1], prob.dt)
+    torch.cuda.synchronize()
+    for x, y in ((a.psi, b.psi), (a.tign, b.tign), (a.frac, b.frac)):
+        assert torch.equal(x, y)
+    assert a.t == b.t
+
+
+def test_boundary_stop_and_continue():
+    n, dx = 64, 6.0
+    fz = np.zeros((n, n))
+    edge = [synth.ignition(3.0, 200.0, t_start=0.0, radius=10.0)]
+    for policy in (0, 1):
+        prob = synth.Problem(n, n, dx, dx, 10, 10, [synth.fuel()], np.zeros((n, n), np.uint8),
+                             fz, fz, edge, 0.5, 5, [(fz + 1.0, fz)], 0,
+                             dict(viscosity=0.4, boundary_policy=policy, guard_width=1))
+        g = gpu_fire(prob, torch.float32)
+        u = torch.ones((n, n), device="cuda")
+        v = torch.zeros((n, n), device="cuda")
+        _, _, rc = g.step(u, v, 0.5, check=False)
+        if policy == 0:
+            assert rc == F.ERR_BOUNDARY
+            psi_before = g.psi.clone()
+            _, _, rc2 = g.step(u, v, 0.5, check=False)
+            assert rc2 == F.ERR_BOUNDARY and torch.equal(psi_before, g.psi)
+        else:
+            assert rc == 0
+            assert g.status() & F.STATUS_BOUNDARY
+    inside = synth.uniform_fire(64, steps=4)
+    g = gpu_fire(inside, torch.float32)
+    W = wind_tensors(inside, torch.float32)
+    for _ in range(4):
+        g.step(W[0][0], W[0][1], inside.dt)
+    assert g.status() == 0
+
+
+def test_nonfinite_state_is_reported():
+    prob = synth.uniform_fire(48, steps=2)
+    g = gpu_fire(prob, torch.float32, boundary_policy=1)
+    psi = torch.full((48, 48), 50.0, device="cuda")
+    psi[20, 20] = float("nan")
+    g.set_state(psi, torch.full((48, 48), float("inf"), device="cuda"),
+                torch.ones((48, 48), device="cuda"), 0.0)
+    W = wind_tensors(prob, torch.float32)
+    g.step(W[0][0], W[0][1], prob.dt)
+    assert g.status() & F.STATUS_NONFINITE
+
+
+def test_invalid_arguments_raise():
+    prob = synth.uniform_fire(32)
+    g = gpu_fire(prob, torch.float32)
+    W = wind_tensors(prob, torch.float32)
+    with pytest.raises(F.FireError):
+        g.step(W[0][0], W[0][1], 0.0)
+    with pytest.raises(F.FireError):
+        g.set_tile(125, 10)
+    with pytest.raises(F.FireError):
+        g.set_tile(120, 15)
+    with pytest.raises(ValueError):
+        g.step(W[0][0].double(), W[0][1].double(), 0.5)

@@ -19,7 +19,6 @@ constexpr int kFW = 128;
 constexpr int kNR = 4;
 constexpr int kHalo = 3;
 constexpr int kFHMax = 32;
-constexpr int kRowsPerThread = kFHMax / kNR;
 constexpr int kTileXMax = kFW - 2 * kHalo;      // 122
 constexpr int kTileYMax = kFHMax - 2 * kHalo;   // 26
 constexpr int kBlock = kFW * kNR;

@@ -31,12 +31,14 @@ template <> struct M<float> {
         return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(x));
     }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) {
         return a * __builtin_amdgcn_rcpf(b);
     }
-    // 1 - exp(-x) without cancellation for small x
-    static __device__ __forceinline__ float one_m_exp_neg(float x) { return -expm1f(-x); }
+    // 1 - exp(-x); its absolute rounding error is that of F itself
+    static __device__ __forceinline__ float one_m_exp_neg(float x) {
+        return 1.0f - __builtin_amdgcn_exp2f(-1.4426950408889634f * x);
+    }
     static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
 };
 
@@ -82,30 +84,53 @@ template <typename T> __device__ __forceinline__ T ghost(T pb, T pb1) {
 }
 
 template <typename T> struct Consts {
-    T dx, dy, rdx, rdy, r2dx, r2dy, eps, cap;
+    T rdx, rdy, eps, cap;
     int visc_mode;
 };
 
+// Per-category row of the in-LDS table, the multiplier m_k folded in
+// (m max{S0, R0 + c U^b + d g^2} = max{m S0, m R0 + m c U^b + m d g^2}, m >= 0).
+enum { kLR0, kLC, kLD, kLB, kLE, kLS0, kLTf, kLCh, kLCq, kLPad0, kLPad1, kLPad2, kLRow };
+
+template <typename T> struct alignas(4 * sizeof(T)) V4 { T x, y, z, w; };
+
+// Spread rate, Eq. (3), with multiplier and cap, from an LDS table row.
+template <typename T>
+__device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
+    const V4<T> r0 = *reinterpret_cast<const V4<T> *>(row);       // R0 c d b
+    const V4<T> r1 = *reinterpret_cast<const V4<T> *>(row + 4);   // e S0 Tf Ch
+    T U = un > T(0) ? un : T(0);
+    U = U > r1.x ? r1.x : U;
+    const T g = tn > T(0) ? tn : T(0);
+    T s = r0.x + r0.y * M<T>::powp(U, r0.w) + r0.z * (g * g);
+    s = s < r1.y ? r1.y : s;
+    return s > cap ? cap : s;
+}
+
 // Right-hand side of Eq. (12) at frame cell (fy, fx) of the level set P.
+// The Godunov choice of Eq. (13) enters only through its square, which for
+// every sign pattern is max(max(D-,0)^2, min(D+,0)^2); the dx-scaled
+// Laplacian is (D+ - D-) summed over x and y.  The central gradient is taken
+// as (psi_E - psi_W)/dx (its factor 1/2 cancels in the normal) straight from
+// the two nodes, so it is exactly zero when they are equal -- as at a domain
+// corner whose ghosts mirror the inner nodes -- whatever the compiler fuses.
 template <typename T>
 __device__ __forceinline__ T rhs(const T (*P)[kFW], int fy, int fx, T u, T v, T gzx, T gzy,
                                  const T *row, const Consts<T> &c) {
     const T pc = P[fy][fx], pw = P[fy][fx - 1], pe = P[fy][fx + 1];
     const T ps = P[fy - 1][fx], pn = P[fy + 1][fx];
-    const T gx = godunov((pc - pw) * c.rdx, (pe - pc) * c.rdx);
-    const T gy = godunov((pc - ps) * c.rdy, (pn - pc) * c.rdy);
-    const T up = M<T>::sqrt(gx * gx + gy * gy);
-    // normal from central differences; zero where the gradient vanishes
-    const T cx = (pe - pw) * c.r2dx, cy = (pn - ps) * c.r2dy;
+    const T dmx = (pc - pw) * c.rdx, dpx = (pe - pc) * c.rdx;
+    const T dmy = (pc - ps) * c.rdy, dpy = (pn - pc) * c.rdy;
+    const T ax = dmx > T(0) ? dmx : T(0), bx = dpx < T(0) ? dpx : T(0);
+    const T ay = dmy > T(0) ? dmy : T(0), by = dpy < T(0) ? dpy : T(0);
+    const T gx2 = tmax(ax * ax, bx * bx), gy2 = tmax(ay * ay, by * by);
+    const T up = M<T>::sqrt(gx2 + gy2);
+    const T cx = (pe - pw) * c.rdx, cy = (pn - ps) * c.rdy;
     const T cn2 = cx * cx + cy * cy;
-    T nx = T(0), ny = T(0);
-    if (cn2 > T(0)) {
-        const T inv = M<T>::rsqrt(cn2);
-        nx = cx * inv;
-        ny = cy * inv;
-    }
-    const T S = ros(row, u * nx + v * ny, gzx * nx + gzy * ny, c.cap);
-    const T lap = (pe - T(2) * pc + pw) * c.rdx + (pn - T(2) * pc + ps) * c.rdy;
+    const T inv = cn2 > T(0) ? M<T>::rsqrt(cn2) : T(0);
+    const T nx = cx * inv, ny = cy * inv;
+    const T S = ros_row(row, u * nx + v * ny, gzx * nx + gzy * ny, c.cap);
+    const T lap = (dpx - dmx) + (dpy - dmy);
     const T visc = c.visc_mode == 0 ? c.eps * S * lap : c.eps * lap;
     return visc - S * up;
 }
@@ -182,19 +207,68 @@ __device__ __forceinline__ void ghost_node(T (*P)[kFW], int fy, int fx, int gx, 
     }
 }
 
+// Fuel fraction of one cell at t' (Eqs. 15-19) from the 3x3 node values of
+// psi^{n+1} (A) and of the node ignition times t^ (B, already t' where
+// psi >= 0).  Four sub-cells with corners at the centre, two edge midpoints
+// and a cell corner, bilinear values, t^ reset to t' where psi >= 0 there.
 template <typename T>
+__device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*B)[kFW], int fy, int fx,
+                                           T tp, T rTf) {
+    T p[3][3], q[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            p[b][a] = A[fy + b - 1][fx + a - 1];
+            q[b][a] = B[fy + b - 1][fx + a - 1];
+        }
+    // edge midpoints and corners shared by neighbouring sub-cells
+    const T pc = p[1][1], qc = q[1][1];
+    T pe[2][2], qe[2][2];   // [0][s]: x edges (s = left/right), [1][s]: y edges
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        pe[0][s] = T(0.5) * (pc + p[1][2 * s]);
+        qe[0][s] = T(0.5) * (qc + q[1][2 * s]);
+        pe[1][s] = T(0.5) * (pc + p[2 * s][1]);
+        qe[1][s] = T(0.5) * (qc + q[2 * s][1]);
+    }
+    T burned = T(0);
+#pragma unroll
+    for (int sb = 0; sb < 2; sb++)
+#pragma unroll
+        for (int sa = 0; sa < 2; sa++) {
+            const T pk[4] = {pc, pe[0][sa], pe[1][sb],
+                             T(0.25) * (pc + p[1][2 * sa] + p[2 * sb][1] + p[2 * sb][2 * sa])};
+            const T qk[4] = {qc, qe[0][sa], qe[1][sb],
+                             T(0.25) * (qc + q[1][2 * sa] + q[2 * sb][1] + q[2 * sb][2 * sa])};
+            T sum = T(0), asum = T(0), tau = T(0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                sum += pk[k];
+                asum += tabs(pk[k]);
+                tau += pk[k] >= T(0) ? T(0) : (tp - qk[k]);
+            }
+            const T beta = asum > T(0) ? T(0.5) * (T(1) - M<T>::div(sum, asum)) : T(0);
+            burned += beta * M<T>::one_m_exp_neg(T(0.25) * tau * rTf);
+        }
+    return T(1) - T(0.25) * burned;
+}
+
+// The fused step.  KR = frame rows per thread (frame height <= 4 KR).
+template <typename T, int KR>
 __global__ void __launch_bounds__(kBlock)
 k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
        const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
        const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
        T *__restrict__ fsens, T *__restrict__ flat, int *status) {
-    __shared__ T A[kFHMax][kFW];
-    __shared__ T B[kFHMax][kFW];
-    extern __shared__ double dyn_smem[];
+    constexpr int FHM = kNR * KR;
+    __shared__ T A[FHM][kFW];
+    __shared__ T B[FHM][kFW];
+    extern __shared__ __attribute__((aligned(32))) double dyn_smem[];
     T *tab = reinterpret_cast<T *>(dyn_smem);
 
     // XCD-aware tile order: work-group b runs on XCD b % 8; give each XCD a
-    // contiguous range of row-major tiles.
+    // contiguous range of row-major tiles so halo rows stay in its L2.
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
     if (tile >= a.ntiles) return;
@@ -207,147 +281,153 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     const int FH = a.tile_y + 2 * kHalo;
     const int gx = x0 - kHalo + tx;
     const bool colin = gx >= 0 && gx < nx;
-    const bool xr1 = tx >= 1 && tx < a.tile_x + 5;
-    const bool xr2 = tx >= 2 && tx < a.tile_x + 4;
-    const bool xr3 = tx >= 3 && tx < a.tile_x + 3;
+    const bool xr1 = colin && tx >= 1 && tx < a.tile_x + 5;
+    const bool xr2 = colin && tx >= 2 && tx < a.tile_x + 4;
+    const bool xr3 = colin && tx >= 3 && tx < a.tile_x + 3;
+    // frame rows [r_lo, r_hi) of region k that lie inside the domain
+    const int ylo = kHalo - y0 > 0 ? kHalo - y0 : 0;          // first in-domain frame row
+    const int yhi = ny - y0 + kHalo < FH ? ny - y0 + kHalo : FH;
 
-    for (int i = tid; i < a.ncat * kNCoef; i += kBlock) tab[i] = coef[i];
+    for (int i = tid; i < a.ncat; i += kBlock) {
+        const T *g = coef + i * kNCoef;
+        T *r = tab + i * kLRow;
+        const T m = g[kM];
+        r[kLR0] = m * g[kR0];
+        r[kLC] = m * g[kC];
+        r[kLD] = m * g[kD];
+        r[kLB] = g[kB];
+        r[kLE] = g[kE];
+        r[kLS0] = m * g[kS0];
+        r[kLTf] = T(1) / g[kTf];
+        r[kLCh] = g[kCh];
+        r[kLCq] = g[kCq];
+        r[kLPad0] = r[kLPad1] = r[kLPad2] = T(0);
+    }
 
     Consts<T> c;
-    c.dx = T(a.dx);
-    c.dy = T(a.dy);
     c.rdx = T(1.0 / a.dx);
     c.rdy = T(1.0 / a.dy);
-    c.r2dx = T(0.5 / a.dx);
-    c.r2dy = T(0.5 / a.dy);
     c.eps = T(a.eps);
     c.cap = T(a.ros_cap);
     c.visc_mode = a.visc_mode;
     const T dt = T(a.dt);
+    const T hdt = T(0.5 * a.dt);
     const T t = T(a.t);
     const T tp = T(a.t + a.dt);
     const T INF = M<T>::inf();
 
-    // ---- load: psi everywhere in the frame, inputs where they are used
-    T p0[kRowsPerThread], uu[kRowsPerThread], vv[kRowsPerThread];
-    T zx[kRowsPerThread], zy[kRowsPerThread], told[kRowsPerThread], fold[kRowsPerThread];
-    T tig[kRowsPerThread];
-    int cc[kRowsPerThread];
+    // ---- load psi^n on the whole frame and step 1, ignition (Sect. 4.4):
+    // psi := min(psi, psi_g); a node lit by this step's ignitions gets the
+    // earliest arrival among the ignitions that cover it
+    T tig[KR];
+    T p0[KR];
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        const int gy = y0 - kHalo + fy;
-        const bool in = colin && fy < FH && gy >= 0 && gy < ny;
-        const bool r1 = in && xr1 && fy >= 1 && fy < a.tile_y + 5;
-        const bool r2 = in && xr2 && fy >= 2 && fy < a.tile_y + 4;
-        const bool r3 = in && xr3 && fy >= 3 && fy < a.tile_y + 3;
-        const size_t idx = in ? (size_t)gy * nx + gx : 0;
+        const bool in = colin && fy >= ylo && fy < yhi;
+        const size_t idx = (size_t)(y0 - kHalo + fy) * nx + gx;
         p0[k] = in ? psi_in[idx] : T(0);
-        uu[k] = r1 ? uw[idx] : T(0);
-        vv[k] = r1 ? vw[idx] : T(0);
-        zx[k] = r1 ? dzdx[idx] : T(0);
-        zy[k] = r1 ? dzdy[idx] : T(0);
-        const int cv = r1 ? (int)cat[idx] : 0;
-        cc[k] = cv < a.ncat ? cv : a.ncat - 1;   // the caller guarantees cv < ncat
-        told[k] = r2 ? tign[idx] : INF;
-        fold[k] = r3 ? frac[idx] : T(1);
         tig[k] = INF;
     }
-
-    // ---- step 1, ignition: psi := min(psi, psi_g); newly ignited nodes get
-    // the earliest arrival among the ignitions covering them (Sect. 4.4)
-    for (int g = 0; g < a.nign; g++) {
-        IgnGeo<T> geo;
-        if (!ign_setup<T>(a.ign[g], a.t, geo)) continue;
-        const double xg = ((double)gx + 0.5) * a.dx;
-#pragma unroll
-        for (int k = 0; k < kRowsPerThread; k++) {
-            const int fy = ty + kNR * k;
-            const double yg = ((double)(y0 - kHalo + fy) + 0.5) * a.dy;
-            T arr;
-            const T pg = ign_psi(geo, xg, yg, arr);
-            // earliest arrival among the ignitions covering the node; it
-            // counts below only where this step's ignition lit the node
-            if (pg <= T(0) && arr < tig[k]) tig[k] = arr;
-            if (pg < p0[k]) p0[k] = pg;
-        }
-    }
     if (a.nign > 0) {
-        // tig holds the earliest covering arrival; it counts only where the
-        // ignition turned psi from > 0 to <= 0
+        T pold[KR];
 #pragma unroll
-        for (int k = 0; k < kRowsPerThread; k++) {
-            const int fy = ty + kNR * k;
-            const int gy = y0 - kHalo + fy;
-            const bool in = colin && fy < FH && gy >= 0 && gy < ny;
-            const size_t idx = in ? (size_t)gy * nx + gx : 0;
-            const T pold = in ? psi_in[idx] : T(0);
-            if (!(pold > T(0) && p0[k] <= T(0))) tig[k] = INF;
+        for (int k = 0; k < KR; k++) pold[k] = p0[k];
+        const double xg = ((double)gx + 0.5) * a.dx;
+        for (int g = 0; g < a.nign; g++) {
+            IgnGeo<T> geo;
+            if (!ign_setup<T>(a.ign[g], a.t, geo)) continue;
+#pragma unroll
+            for (int k = 0; k < KR; k++) {
+                const double yg = ((double)(y0 - kHalo + ty + kNR * k) + 0.5) * a.dy;
+                T arr;
+                const T pg = ign_psi(geo, xg, yg, arr);
+                if (pg <= T(0) && arr < tig[k]) tig[k] = arr;
+                if (pg < p0[k]) p0[k] = pg;
+            }
         }
-    }
-
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+        for (int k = 0; k < KR; k++)
+            if (!(pold[k] > T(0) && p0[k] <= T(0))) tig[k] = INF;
+    }
+#pragma unroll
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (fy < FH) A[fy][tx] = p0[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (fy < FH) ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
     }
     __syncthreads();
 
-    // ---- step 2a, first Heun stage on the tile plus two rings
-    T F1[kRowsPerThread];
+    // ---- step 2a: first Heun stage on the tile plus two rings,
+    // psi* = psi^n + dt F(psi^n)
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        const int gy = y0 - kHalo + fy;
-        const bool r1 = colin && xr1 && fy >= 1 && fy < a.tile_y + 5 && gy >= 0 && gy < ny;
-        F1[k] = T(0);
-        if (r1) {
-            F1[k] = rhs(A, fy, tx, uu[k], vv[k], zx[k], zy[k], tab + cc[k] * kNCoef, c);
-            B[fy][tx] = p0[k] + dt * F1[k];
+        if (xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi) {
+            const size_t idx = (size_t)(y0 - kHalo + fy) * nx + gx;
+            const int cv = cat[idx];
+            const T *row = tab + (cv < a.ncat ? cv : a.ncat - 1) * kLRow;
+            const T F1 = rhs(A, fy, tx, uw[idx], vw[idx], dzdx[idx], dzdy[idx], row, c);
+            B[fy][tx] = p0[k] + dt * F1;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (fy < FH) ghost_node(B, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
     }
     __syncthreads();
 
-    // ---- step 2b, second stage on the tile plus one ring; step 3, ignition
+    // ---- step 2b: second stage on the tile plus one ring,
+    // psi^{n+1} = (psi^n + psi* + dt F(psi*))/2, Eq. (11); step 3: ignition
     // time of nodes crossed during the step (Eq. 14), first crossing kept
-    T p1[kRowsPerThread], tnew[kRowsPerThread], that[kRowsPerThread];
+    T that[KR];
+    int st = 0;
+    const int gw = a.guard;
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        const int gy = y0 - kHalo + fy;
-        const bool r2 = colin && xr2 && fy >= 2 && fy < a.tile_y + 4 && gy >= 0 && gy < ny;
-        p1[k] = T(0);
-        tnew[k] = told[k];
         that[k] = tp;
-        if (r2) {
-            const T F2 = rhs(B, fy, tx, uu[k], vv[k], zx[k], zy[k], tab + cc[k] * kNCoef, c);
-            const T pn = p0[k] + dt * (T(0.5) * F1[k] + T(0.5) * F2);
-            p1[k] = pn;
-            A[fy][tx] = pn;  // stage-1 reads of A finished at the last barrier
-            T ti = told[k];
-            if (is_inf(ti) && tig[k] < INF) ti = tig[k];
-            if (p0[k] > T(0) && pn <= T(0) && is_inf(ti)) ti = t + M<T>::div(p0[k] * dt, p0[k] - pn);
-            tnew[k] = ti;
+        if (xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi) {
+            const int gy = y0 - kHalo + fy;
+            const size_t idx = (size_t)gy * nx + gx;
+            const int cv = cat[idx];
+            const T *row = tab + (cv < a.ncat ? cv : a.ncat - 1) * kLRow;
+            const T F2 = rhs(B, fy, tx, uw[idx], vw[idx], dzdx[idx], dzdy[idx], row, c);
+            const T pn0 = A[fy][tx];
+            const T pn = T(0.5) * (pn0 + B[fy][tx]) + hdt * F2;
+            A[fy][tx] = pn;   // stage-1 reads of A ended at the last barrier
+            // t_i is read only where it can matter: a burning node, a node
+            // crossing zero, or a node lit by this step's ignition
+            T ti = INF, told = INF;
+            if (pn <= T(0) || tig[k] < INF) {
+                told = tign[idx];
+                ti = told;
+                if (is_inf(ti)) ti = tig[k];
+                if (pn0 > T(0) && pn <= T(0) && is_inf(ti))
+                    ti = t + M<T>::div(pn0 * dt, pn0 - pn);
+            }
             that[k] = pn >= T(0) ? tp : ti;   // Eq. (17)
+            if (xr3 && fy >= 3 && fy < a.tile_y + 3) {
+                psi_out[idx] = pn;
+                if (!(ti == told)) tign[idx] = ti;
+                const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
+                if (edge && pn < T(0)) st |= kStBoundary;
+                if (!__builtin_isfinite(pn)) st |= kStNonfinite;
+            }
         }
     }
     __syncthreads();
     // node ignition times for the quadrature; ghost nodes get t' (reading
-    // R19), ghost psi is re-extrapolated including corners
+    // R19); ghost psi is re-extrapolated, corners included
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (fy < FH) {
             B[fy][tx] = that[k];
@@ -357,66 +437,40 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     __syncthreads();
 
     // ---- steps 4-5: fuel fraction at t' (Eqs. 15-19) and cell fluxes
-    T fs[kRowsPerThread], fl[kRowsPerThread];
-    int st = 0;
-    const int gw = a.guard;
+    // (Eqs. 5-6).  A cell whose nine stencil nodes all have psi >= 0 has no
+    // burning sub-cell point: beta = 0 in every sub-cell and F = 1 exactly.
+    T fs[KR], fl[KR];
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        const int gy = y0 - kHalo + fy;
-        const bool r3 = colin && xr3 && fy >= 3 && fy < a.tile_y + 3 && gy >= 0 && gy < ny;
         fs[k] = T(0);
         fl[k] = T(0);
-        if (r3) {
-            const T *row = tab + cc[k] * kNCoef;
-            const T pc = A[fy][tx], tc = B[fy][tx];
-            T burned = T(0);
+        if (xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi) {
+            const size_t idx = (size_t)(y0 - kHalo + fy) * nx + gx;
+            const T fo = frac[idx];
+            const int cv = cat[idx];
+            const T *row = tab + (cv < a.ncat ? cv : a.ncat - 1) * kLRow;
+            T mn = A[fy][tx];
 #pragma unroll
-            for (int sb = -1; sb <= 1; sb += 2) {
+            for (int b = -1; b <= 1; b++)
 #pragma unroll
-                for (int sa = -1; sa <= 1; sa += 2) {
-                    const T pxe = A[fy][tx + sa], pye = A[fy + sb][tx], pxy = A[fy + sb][tx + sa];
-                    const T txe = B[fy][tx + sa], tye = B[fy + sb][tx], txy = B[fy + sb][tx + sa];
-                    T ps[4], ts[4];
-                    ps[0] = pc;
-                    ts[0] = tc;
-                    ps[1] = T(0.5) * (pc + pxe);
-                    ts[1] = T(0.5) * (tc + txe);
-                    ps[2] = T(0.5) * (pc + pye);
-                    ts[2] = T(0.5) * (tc + tye);
-                    ps[3] = T(0.25) * (pc + pxe + pye + pxy);
-                    ts[3] = T(0.25) * (tc + txe + tye + txy);
-                    T s = T(0), as = T(0), tau = T(0);
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        s += ps[q];
-                        as += tabs(ps[q]);
-                        tau += ps[q] >= T(0) ? T(0) : (tp - ts[q]);
-                    }
-                    const T beta = as > T(0) ? T(0.5) * (T(1) - M<T>::div(s, as)) : T(0);
-                    tau = M<T>::div(T(0.25) * tau, row[kTf]);
-                    burned += beta * M<T>::one_m_exp_neg(tau);
-                }
-            }
-            const T Fn = T(1) - T(0.25) * burned;
-            const T dF = M<T>::div(fold[k] - Fn, dt);
-            fs[k] = dF * row[kCh];
-            fl[k] = dF * row[kCq];
-            const size_t idx = (size_t)gy * nx + gx;
-            psi_out[idx] = p1[k];
-            frac[idx] = Fn;
-            if (!(tnew[k] == told[k])) tign[idx] = tnew[k];
-            const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
-            if (edge && p1[k] < T(0)) st |= kStBoundary;
-            if (!__builtin_isfinite(p1[k]) || !__builtin_isfinite(Fn)) st |= kStNonfinite;
+                for (int d = -1; d <= 1; d++) mn = mn < A[fy + b][tx + d] ? mn : A[fy + b][tx + d];
+            T Fn = T(1);
+            if (mn < T(0)) Fn = cell_fraction(A, B, fy, tx, tp, row[kLTf]);
+            const T dF = M<T>::div(fo - Fn, dt);
+            fs[k] = dF * row[kLCh];
+            fl[k] = dF * row[kLCq];
+            if (!(Fn == fo)) frac[idx] = Fn;
+            if (!__builtin_isfinite(Fn)) st |= kStNonfinite;
         }
     }
     if (st) atomicOr(status, st);
     __syncthreads();
 
-    // ---- step 6: mean flux over each atmosphere cell of the tile
+    // ---- step 6: mean flux over each atmosphere cell of the tile, summed
+    // in a fixed order (columns, then the column sums)
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; k++) {
+    for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (fy < FH) {
             A[fy][tx] = fs[k];
@@ -425,9 +479,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     }
     __syncthreads();
     const int nI = a.tile_x / a.sr_x, nJ = a.tile_y / a.sr_y;
-    if (xr3) {
-        // column sums over the sr_y rows of each atmosphere row, written into
-        // the first row of the block (read before written, by this thread only)
+    if (tx >= kHalo && tx < a.tile_x + kHalo) {
         for (int J = ty; J < nJ; J += kNR) {
             const int r0 = kHalo + J * a.sr_y;
             T s1 = T(0), s2 = T(0);
@@ -435,7 +487,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
                 s1 += A[r0 + r][tx];
                 s2 += B[r0 + r][tx];
             }
-            A[r0][tx] = s1;
+            A[r0][tx] = s1;   // read above by this thread only
             B[r0][tx] = s2;
         }
     }
@@ -547,15 +599,26 @@ template <typename T> __global__ void k_to_f64(const T *src, double *dst, int n)
     if (i < n) dst[i] = (double)src[i];
 }
 
-template <typename T>
-hipError_t step_t(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
-    const size_t dyn = (size_t)a.ncat * kNCoef * sizeof(T);
+template <typename T, int KR>
+hipError_t step_k(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
+    const size_t dyn = (size_t)a.ncat * kLRow * sizeof(T);
     const int grid = a.per_xcd * 8;
-    hipLaunchKernelGGL((k_step<T>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+    hipLaunchKernelGGL((k_step<T, KR>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
                        (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
                        (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
                        b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
     return hipGetLastError();
+}
+
+// frame height tile_y + 6 <= 4 KR
+template <typename T>
+hipError_t step_t(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
+    const int fh = a.tile_y + 2 * kHalo;
+    if (fh <= 16) return step_k<T, 4>(a, b, s);
+    if (fh <= 20) return step_k<T, 5>(a, b, s);
+    if (fh <= 24) return step_k<T, 6>(a, b, s);
+    if (fh <= 28) return step_k<T, 7>(a, b, s);
+    return step_k<T, 8>(a, b, s);
 }
 
 }  // namespace

@@ -51,36 +51,30 @@ template <> struct M<double> {
     static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
 };
 
-template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
-template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+// max / min / |.| as single instructions (for non-NaN operands the same as
+// the comparisons they replace; a NaN operand yields the other one)
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float vabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double vabs(double a) { return __builtin_fabs(a); }
 template <typename T> __device__ __forceinline__ bool is_inf(T a) { return a == M<T>::inf(); }
 
 // Spread rate, Eq. (3), with the category multiplier and the cap:
 // S = min{cap, m max{S0, R0 + c min{e, max{0,U}}^b + d max{0, tan phi}^2}}.
 template <typename T>
 __device__ __forceinline__ T ros(const T *row, T un, T tn, T cap) {
-    T U = un > T(0) ? un : T(0);
-    U = U > row[kE] ? row[kE] : U;
-    T g = tn > T(0) ? tn : T(0);
+    const T U = vmin(vmax(un, T(0)), row[kE]);
+    const T g = vmax(tn, T(0));
     T s = row[kR0] + row[kC] * M<T>::powp(U, row[kB]) + row[kD] * g * g;
-    s = s < row[kS0] ? row[kS0] : s;
-    s = row[kM] * s;
-    return s > cap ? cap : s;
-}
-
-// Godunov upwind selection of Eq. (13), cases taken in the printed order.
-template <typename T> __device__ __forceinline__ T godunov(T dm, T dp) {
-    if (dm <= T(0) && dp <= T(0)) return dp;
-    if (dm >= T(0) && dp >= T(0)) return dm;
-    if (dm <= T(0) && dp >= T(0)) return T(0);
-    return tabs(dm) >= tabs(dp) ? dm : dp;
+    s = vmax(s, row[kS0]);
+    return vmin(row[kM] * s, cap);
 }
 
 // Boundary extrapolation of Sect. 4.1: never below either source node.
 template <typename T> __device__ __forceinline__ T ghost(T pb, T pb1) {
-    T lin = pb + (pb - pb1);
-    T m = pb > pb1 ? pb : pb1;
-    return lin > m ? lin : m;
+    return vmax(pb + (pb - pb1), vmax(pb, pb1));
 }
 
 template <typename T> struct Consts {
@@ -99,12 +93,10 @@ template <typename T>
 __device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
     const V4<T> r0 = *reinterpret_cast<const V4<T> *>(row);       // R0 c d b
     const V4<T> r1 = *reinterpret_cast<const V4<T> *>(row + 4);   // e S0 Tf Ch
-    T U = un > T(0) ? un : T(0);
-    U = U > r1.x ? r1.x : U;
-    const T g = tn > T(0) ? tn : T(0);
-    T s = r0.x + r0.y * M<T>::powp(U, r0.w) + r0.z * (g * g);
-    s = s < r1.y ? r1.y : s;
-    return s > cap ? cap : s;
+    const T U = vmin(vmax(un, T(0)), r1.x);
+    const T g = vmax(tn, T(0));
+    const T s = r0.x + r0.y * M<T>::powp(U, r0.w) + r0.z * (g * g);
+    return vmin(vmax(s, r1.y), cap);
 }
 
 // Right-hand side of Eq. (12) at frame cell (fy, fx) of the level set P.
@@ -121,9 +113,9 @@ __device__ __forceinline__ T rhs(const T (*P)[kFW], int fy, int fx, T u, T v, T 
     const T ps = P[fy - 1][fx], pn = P[fy + 1][fx];
     const T dmx = (pc - pw) * c.rdx, dpx = (pe - pc) * c.rdx;
     const T dmy = (pc - ps) * c.rdy, dpy = (pn - pc) * c.rdy;
-    const T ax = dmx > T(0) ? dmx : T(0), bx = dpx < T(0) ? dpx : T(0);
-    const T ay = dmy > T(0) ? dmy : T(0), by = dpy < T(0) ? dpy : T(0);
-    const T gx2 = tmax(ax * ax, bx * bx), gy2 = tmax(ay * ay, by * by);
+    const T ax = vmax(dmx, T(0)), bx = vmin(dpx, T(0));
+    const T ay = vmax(dmy, T(0)), by = vmin(dpy, T(0));
+    const T gx2 = vmax(ax * ax, bx * bx), gy2 = vmax(ay * ay, by * by);
     const T up = M<T>::sqrt(gx2 + gy2);
     const T cx = (pe - pw) * c.rdx, cy = (pn - ps) * c.rdy;
     const T cn2 = cx * cx + cy * cy;
@@ -208,11 +200,11 @@ __device__ __forceinline__ void ghost_node(T (*P)[kFW], int fy, int fx, int gx, 
 }
 
 // Fuel fraction of one cell at t' (Eqs. 15-19) from the 3x3 node values of
-// psi^{n+1} (A) and of the node ignition times t^ (B, already t' where
+// psi^{n+1} (A) and of the node ignition times t^ (Q, already t' where
 // psi >= 0).  Four sub-cells with corners at the centre, two edge midpoints
 // and a cell corner, bilinear values, t^ reset to t' where psi >= 0 there.
 template <typename T>
-__device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*B)[kFW], int fy, int fx,
+__device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW], int fy, int fx,
                                            T tp, T rTf) {
     T p[3][3], q[3][3];
 #pragma unroll
@@ -220,7 +212,7 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*B)[kFW],
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             p[b][a] = A[fy + b - 1][fx + a - 1];
-            q[b][a] = B[fy + b - 1][fx + a - 1];
+            q[b][a] = Q[fy + b - 1][fx + a - 1];
         }
     // edge midpoints and corners shared by neighbouring sub-cells
     const T pc = p[1][1], qc = q[1][1];
@@ -245,7 +237,7 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*B)[kFW],
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 sum += pk[k];
-                asum += tabs(pk[k]);
+                asum += vabs(pk[k]);
                 tau += pk[k] >= T(0) ? T(0) : (tp - qk[k]);
             }
             const T beta = asum > T(0) ? T(0.5) * (T(1) - M<T>::div(sum, asum)) : T(0);
@@ -255,6 +247,8 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*B)[kFW],
 }
 
 // The fused step.  KR = frame rows per thread (frame height <= 4 KR).
+// LDS frames: A holds psi^n, then psi^{n+1}, then the latent flux; B holds
+// psi*, then the sensible flux; C holds the node ignition times t^.
 template <typename T, int KR>
 __global__ void __launch_bounds__(kBlock)
 k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
@@ -264,6 +258,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     constexpr int FHM = kNR * KR;
     __shared__ T A[FHM][kFW];
     __shared__ T B[FHM][kFW];
+    __shared__ T C[FHM][kFW];
     extern __shared__ __attribute__((aligned(32))) double dyn_smem[];
     T *tab = reinterpret_cast<T *>(dyn_smem);
 
@@ -284,9 +279,13 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     const bool xr1 = colin && tx >= 1 && tx < a.tile_x + 5;
     const bool xr2 = colin && tx >= 2 && tx < a.tile_x + 4;
     const bool xr3 = colin && tx >= 3 && tx < a.tile_x + 3;
-    // frame rows [r_lo, r_hi) of region k that lie inside the domain
-    const int ylo = kHalo - y0 > 0 ? kHalo - y0 : 0;          // first in-domain frame row
+    // in-domain frame rows [ylo, yhi)
+    const int ylo = kHalo - y0 > 0 ? kHalo - y0 : 0;
     const int yhi = ny - y0 + kHalo < FH ? ny - y0 + kHalo : FH;
+    // a frame that lies inside the domain has no ghost nodes
+    const bool interior = x0 >= kHalo && x0 + a.tile_x + kHalo <= nx && ylo == 0 && yhi == FH;
+    // global offset of frame row 0 (row offsets stay 32-bit: nx * ny < 2^31)
+    const int off0 = (y0 - kHalo) * nx + gx;
 
     for (int i = tid; i < a.ncat; i += kBlock) {
         const T *g = coef + i * kNCoef;
@@ -315,6 +314,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     const T t = T(a.t);
     const T tp = T(a.t + a.dt);
     const T INF = M<T>::inf();
+    const int ncm1 = a.ncat - 1;
 
     // ---- load psi^n on the whole frame and step 1, ignition (Sect. 4.4):
     // psi := min(psi, psi_g); a node lit by this step's ignitions gets the
@@ -325,8 +325,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         const bool in = colin && fy >= ylo && fy < yhi;
-        const size_t idx = (size_t)(y0 - kHalo + fy) * nx + gx;
-        p0[k] = in ? psi_in[idx] : T(0);
+        p0[k] = in ? psi_in[off0 + fy * nx] : T(0);
         tig[k] = INF;
     }
     if (a.nign > 0) {
@@ -343,7 +342,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
                 T arr;
                 const T pg = ign_psi(geo, xg, yg, arr);
                 if (pg <= T(0) && arr < tig[k]) tig[k] = arr;
-                if (pg < p0[k]) p0[k] = pg;
+                if (pg < p0[k]) p0[k] = pg;   // a NaN psi stays NaN (status word)
             }
         }
 #pragma unroll
@@ -356,12 +355,14 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         if (fy < FH) A[fy][tx] = p0[k];
     }
     __syncthreads();
+    if (!interior) {
 #pragma unroll
-    for (int k = 0; k < KR; k++) {
-        const int fy = ty + kNR * k;
-        if (fy < FH) ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+        for (int k = 0; k < KR; k++) {
+            const int fy = ty + kNR * k;
+            if (fy < FH) ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- step 2a: first Heun stage on the tile plus two rings,
     // psi* = psi^n + dt F(psi^n)
@@ -369,36 +370,37 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi) {
-            const size_t idx = (size_t)(y0 - kHalo + fy) * nx + gx;
+            const int idx = off0 + fy * nx;
             const int cv = cat[idx];
-            const T *row = tab + (cv < a.ncat ? cv : a.ncat - 1) * kLRow;
+            const T *row = tab + (cv < ncm1 ? cv : ncm1) * kLRow;
             const T F1 = rhs(A, fy, tx, uw[idx], vw[idx], dzdx[idx], dzdy[idx], row, c);
             B[fy][tx] = p0[k] + dt * F1;
         }
     }
     __syncthreads();
+    if (!interior) {
 #pragma unroll
-    for (int k = 0; k < KR; k++) {
-        const int fy = ty + kNR * k;
-        if (fy < FH) ghost_node(B, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+        for (int k = 0; k < KR; k++) {
+            const int fy = ty + kNR * k;
+            if (fy < FH) ghost_node(B, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- step 2b: second stage on the tile plus one ring,
     // psi^{n+1} = (psi^n + psi* + dt F(psi*))/2, Eq. (11); step 3: ignition
-    // time of nodes crossed during the step (Eq. 14), first crossing kept
-    T that[KR];
+    // time of nodes crossed during the step (Eq. 14), first crossing kept;
+    // node times t^ = t' where psi^{n+1} >= 0, else t_i (Eq. 17)
     int st = 0;
     const int gw = a.guard;
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        that[k] = tp;
         if (xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi) {
             const int gy = y0 - kHalo + fy;
-            const size_t idx = (size_t)gy * nx + gx;
+            const int idx = off0 + fy * nx;
             const int cv = cat[idx];
-            const T *row = tab + (cv < a.ncat ? cv : a.ncat - 1) * kLRow;
+            const T *row = tab + (cv < ncm1 ? cv : ncm1) * kLRow;
             const T F2 = rhs(B, fy, tx, uw[idx], vw[idx], dzdx[idx], dzdy[idx], row, c);
             const T pn0 = A[fy][tx];
             const T pn = T(0.5) * (pn0 + B[fy][tx]) + hdt * F2;
@@ -413,7 +415,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
                 if (pn0 > T(0) && pn <= T(0) && is_inf(ti))
                     ti = t + M<T>::div(pn0 * dt, pn0 - pn);
             }
-            that[k] = pn >= T(0) ? tp : ti;   // Eq. (17)
+            C[fy][tx] = pn >= T(0) ? tp : ti;
             if (xr3 && fy >= 3 && fy < a.tile_y + 3) {
                 psi_out[idx] = pn;
                 if (!(ti == told)) tign[idx] = ti;
@@ -424,45 +426,47 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         }
     }
     __syncthreads();
-    // node ignition times for the quadrature; ghost nodes get t' (reading
-    // R19); ghost psi is re-extrapolated, corners included
+    if (!interior) {
+        // ghost psi re-extrapolated, corners included; ghost t^ = t' (R19)
 #pragma unroll
-    for (int k = 0; k < KR; k++) {
-        const int fy = ty + kNR * k;
-        if (fy < FH) {
-            B[fy][tx] = that[k];
-            ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, true);
+        for (int k = 0; k < KR; k++) {
+            const int fy = ty + kNR * k;
+            const int gy = y0 - kHalo + fy;
+            if (fy < FH) {
+                ghost_node(A, fy, tx, gx, gy, nx, ny, true);
+                if (!(colin && gy >= 0 && gy < ny)) C[fy][tx] = tp;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- steps 4-5: fuel fraction at t' (Eqs. 15-19) and cell fluxes
     // (Eqs. 5-6).  A cell whose nine stencil nodes all have psi >= 0 has no
     // burning sub-cell point: beta = 0 in every sub-cell and F = 1 exactly.
-    T fs[KR], fl[KR];
+    // The sensible flux goes straight to B (not read in this phase).
+    T fl[KR];
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        fs[k] = T(0);
+        T fs = T(0);
         fl[k] = T(0);
         if (xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi) {
-            const size_t idx = (size_t)(y0 - kHalo + fy) * nx + gx;
+            const int idx = off0 + fy * nx;
             const T fo = frac[idx];
             const int cv = cat[idx];
-            const T *row = tab + (cv < a.ncat ? cv : a.ncat - 1) * kLRow;
-            T mn = A[fy][tx];
-#pragma unroll
-            for (int b = -1; b <= 1; b++)
-#pragma unroll
-                for (int d = -1; d <= 1; d++) mn = mn < A[fy + b][tx + d] ? mn : A[fy + b][tx + d];
+            const T *row = tab + (cv < ncm1 ? cv : ncm1) * kLRow;
+            T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
+            mn = vmin(mn, vmin(vmin(A[fy][tx - 1], A[fy][tx]), A[fy][tx + 1]));
+            mn = vmin(mn, vmin(vmin(A[fy + 1][tx - 1], A[fy + 1][tx]), A[fy + 1][tx + 1]));
             T Fn = T(1);
-            if (mn < T(0)) Fn = cell_fraction(A, B, fy, tx, tp, row[kLTf]);
+            if (mn < T(0)) Fn = cell_fraction(A, C, fy, tx, tp, row[kLTf]);
             const T dF = M<T>::div(fo - Fn, dt);
-            fs[k] = dF * row[kLCh];
+            fs = dF * row[kLCh];
             fl[k] = dF * row[kLCq];
             if (!(Fn == fo)) frac[idx] = Fn;
             if (!__builtin_isfinite(Fn)) st |= kStNonfinite;
         }
+        if (fy < FH) B[fy][tx] = fs;
     }
     if (st) atomicOr(status, st);
     __syncthreads();
@@ -472,10 +476,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        if (fy < FH) {
-            A[fy][tx] = fs[k];
-            B[fy][tx] = fl[k];
-        }
+        if (fy < FH) A[fy][tx] = fl[k];
     }
     __syncthreads();
     const int nI = a.tile_x / a.sr_x, nJ = a.tile_y / a.sr_y;
@@ -484,11 +485,11 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
             const int r0 = kHalo + J * a.sr_y;
             T s1 = T(0), s2 = T(0);
             for (int r = 0; r < a.sr_y; r++) {
-                s1 += A[r0 + r][tx];
-                s2 += B[r0 + r][tx];
+                s1 += B[r0 + r][tx];
+                s2 += A[r0 + r][tx];
             }
-            A[r0][tx] = s1;   // read above by this thread only
-            B[r0][tx] = s2;
+            B[r0][tx] = s1;   // read above by this thread only
+            A[r0][tx] = s2;
         }
     }
     __syncthreads();
@@ -503,8 +504,8 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         const int r0 = kHalo + J * a.sr_y, f0 = kHalo + I * a.sr_x;
         T s1 = T(0), s2 = T(0);
         for (int cI = 0; cI < a.sr_x; cI++) {
-            s1 += A[r0][f0 + cI];
-            s2 += B[r0][f0 + cI];
+            s1 += B[r0][f0 + cI];
+            s2 += A[r0][f0 + cI];
         }
         const T cnt = T(ncx * ncy);
         fsens[(size_t)JG * a.nax + IG] = s1 / cnt;

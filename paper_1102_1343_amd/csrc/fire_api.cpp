@@ -41,7 +41,7 @@ bool mesh_ok(const fire_mesh *m) {
     if ((int64_t)m->nx * m->ny > ((int64_t)1 << 31)) return false;
     if (!(m->dx > 0.0) || !(m->dy > 0.0) || !std::isfinite(m->dx) || !std::isfinite(m->dy))
         return false;
-    if (m->sr_x < 1 || m->sr_x > kTileXMax || m->sr_y < 1 || m->sr_y > kTileYMax) return false;
+    if (m->sr_x < 1 || m->sr_x > kTileXMax || m->sr_y < 1 || m->sr_y > kTileYMax64) return false;
     return m->dtype == FIRE_F32 || m->dtype == FIRE_F64;
 }
 
@@ -219,6 +219,8 @@ int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_s
     a.nign = c->nign;
     a.dx = m.dx;
     a.dy = m.dy;
+    a.rdx = 1.0 / m.dx;
+    a.rdy = 1.0 / m.dy;
     a.t = c->t;
     a.dt = dt;
     a.eps = c->prm.viscosity;
@@ -325,7 +327,8 @@ int fire_ros_eval(fire_ctx *c, const uint8_t *cat, const void *un, const void *t
 int fire_set_tile(fire_ctx *c, int32_t tile_x, int32_t tile_y) {
     if (!c) return FIRE_ERR_ARG;
     if (tile_x < 1 || tile_x > kTileXMax || tile_x % c->mesh.sr_x != 0) return FIRE_ERR_ARG;
-    if (tile_y < 1 || tile_y > kTileYMax || tile_y % c->mesh.sr_y != 0) return FIRE_ERR_ARG;
+    const int ymax = c->mesh.dtype == FIRE_F64 ? kTileYMax64 : kTileYMax;
+    if (tile_y < 1 || tile_y > ymax || tile_y % c->mesh.sr_y != 0) return FIRE_ERR_ARG;
     c->tile_x = tile_x;
     c->tile_y = tile_y;
     return FIRE_OK;

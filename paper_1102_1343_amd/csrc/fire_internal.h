@@ -18,9 +18,10 @@ namespace fire {
 constexpr int kFW = 128;
 constexpr int kNR = 4;
 constexpr int kHalo = 3;
-constexpr int kFHMax = 32;
+constexpr int kFHMax = 48;
 constexpr int kTileXMax = kFW - 2 * kHalo;      // 122
-constexpr int kTileYMax = kFHMax - 2 * kHalo;   // 26
+constexpr int kTileYMax = kFHMax - 2 * kHalo;   // 42
+constexpr int kTileYMax64 = 26;                  // FP64 frames must fit LDS
 constexpr int kBlock = kFW * kNR;
 
 // coefficient table columns (one row per fuel category)
@@ -37,6 +38,7 @@ struct StepArgs {
     int32_t sr_x, sr_y, nax, nay;
     int32_t ncat, guard, visc_mode, nign, pad;
     double dx, dy;
+    double rdx, rdy;     // 1/dx, 1/dy
     double t, dt;
     double eps, ros_cap;
     fire_ignition ign[FIRE_MAX_IGNITIONS];

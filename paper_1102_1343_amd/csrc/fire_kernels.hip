@@ -164,19 +164,34 @@ __device__ __forceinline__ bool ign_setup(const fire_ignition &g, double t, IgnG
     return true;
 }
 
-// psi_g of Eq. (20) (drip-torch form) at the node centred at (x, y) (global
-// metres, double), and the arrival time of the initial fire there, capped
-// at t.
+// psi_g of Eq. (20) (drip-torch form) at the node whose centre is
+// (px, py) away from the segment start (differences formed in double from
+// global coordinates), and the arrival time of the initial fire there,
+// capped at t.
 template <typename T>
-__device__ __forceinline__ T ign_psi(const IgnGeo<T> &g, double x, double y, T &arrive) {
-    const T px = T(x - g.ax), py = T(y - g.ay);
+__device__ __forceinline__ T ign_psi(const IgnGeo<T> &g, T px, T py, T &arrive) {
     T s = (px * g.ex + py * g.ey) * g.invL2;
-    s = s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+    s = vmin(vmax(s, T(0)), T(1));
     const T qx = px - s * g.ex, qy = py - s * g.ey;
     const T d = M<T>::sqrt(qx * qx + qy * qy);
     const T a = g.tg + s * g.lenv + d * g.invS;
-    arrive = a < g.t ? a : g.t;
+    arrive = vmin(a, g.t);
     return d - g.rad;
+}
+
+// Global loads/stores at element index i.  With SMALL (every array below
+// 4 GiB) the byte offset is formed in 32 bits, which lets the compiler use
+// scalar-base addressing with a 32-bit vector offset.
+template <bool SMALL, typename T> __device__ __forceinline__ const T &at(const T *p, uint32_t i) {
+    if (SMALL)
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                            i * (uint32_t)sizeof(T));
+    return p[i];
+}
+template <bool SMALL, typename T> __device__ __forceinline__ T &at(T *p, uint32_t i) {
+    if (SMALL)
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + i * (uint32_t)sizeof(T));
+    return p[i];
 }
 
 // Fill the one-cell ghost ring of frame P around the domain (Sect. 4.1).
@@ -249,7 +264,7 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 // The fused step.  KR = frame rows per thread (frame height <= 4 KR).
 // LDS frames: A holds psi^n, then psi^{n+1}, then the latent flux; B holds
 // psi*, then the sensible flux; C holds the node ignition times t^.
-template <typename T, int KR>
+template <typename T, int KR, bool SMALL>
 __global__ void __launch_bounds__(kBlock)
 k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
        const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
@@ -284,8 +299,9 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     const int yhi = ny - y0 + kHalo < FH ? ny - y0 + kHalo : FH;
     // a frame that lies inside the domain has no ghost nodes
     const bool interior = x0 >= kHalo && x0 + a.tile_x + kHalo <= nx && ylo == 0 && yhi == FH;
-    // global offset of frame row 0 (row offsets stay 32-bit: nx * ny < 2^31)
-    const int off0 = (y0 - kHalo) * nx + gx;
+    // element index of frame row 0 (mod 2^32; in-domain indices are < 2^31)
+    const uint32_t off0 = (uint32_t)((y0 - kHalo) * nx + gx);
+    const uint32_t unx = (uint32_t)nx;
 
     for (int i = tid; i < a.ncat; i += kBlock) {
         const T *g = coef + i * kNCoef;
@@ -304,8 +320,8 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     }
 
     Consts<T> c;
-    c.rdx = T(1.0 / a.dx);
-    c.rdy = T(1.0 / a.dy);
+    c.rdx = T(a.rdx);
+    c.rdy = T(a.rdy);
     c.eps = T(a.eps);
     c.cap = T(a.ros_cap);
     c.visc_mode = a.visc_mode;
@@ -325,7 +341,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         const bool in = colin && fy >= ylo && fy < yhi;
-        p0[k] = in ? psi_in[off0 + fy * nx] : T(0);
+        p0[k] = in ? at<SMALL>(psi_in, off0 + fy * unx) : T(0);
         tig[k] = INF;
     }
     if (a.nign > 0) {
@@ -336,11 +352,12 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         for (int g = 0; g < a.nign; g++) {
             IgnGeo<T> geo;
             if (!ign_setup<T>(a.ign[g], a.t, geo)) continue;
+            const T px = T(xg - geo.ax);
 #pragma unroll
             for (int k = 0; k < KR; k++) {
                 const double yg = ((double)(y0 - kHalo + ty + kNR * k) + 0.5) * a.dy;
                 T arr;
-                const T pg = ign_psi(geo, xg, yg, arr);
+                const T pg = ign_psi(geo, px, T(yg - geo.ay), arr);
                 if (pg <= T(0) && arr < tig[k]) tig[k] = arr;
                 if (pg < p0[k]) p0[k] = pg;   // a NaN psi stays NaN (status word)
             }
@@ -370,10 +387,11 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi) {
-            const int idx = off0 + fy * nx;
-            const int cv = cat[idx];
-            const T *row = tab + (cv < ncm1 ? cv : ncm1) * kLRow;
-            const T F1 = rhs(A, fy, tx, uw[idx], vw[idx], dzdx[idx], dzdy[idx], row, c);
+            const uint32_t idx = off0 + fy * unx;
+            const int cv = at<SMALL>(cat, idx);
+            const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
+            const T F1 = rhs(A, fy, tx, at<SMALL>(uw, idx), at<SMALL>(vw, idx),
+                               at<SMALL>(dzdx, idx), at<SMALL>(dzdy, idx), row, c);
             B[fy][tx] = p0[k] + dt * F1;
         }
     }
@@ -398,10 +416,11 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         const int fy = ty + kNR * k;
         if (xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi) {
             const int gy = y0 - kHalo + fy;
-            const int idx = off0 + fy * nx;
-            const int cv = cat[idx];
-            const T *row = tab + (cv < ncm1 ? cv : ncm1) * kLRow;
-            const T F2 = rhs(B, fy, tx, uw[idx], vw[idx], dzdx[idx], dzdy[idx], row, c);
+            const uint32_t idx = off0 + fy * unx;
+            const int cv = at<SMALL>(cat, idx);
+            const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
+            const T F2 = rhs(B, fy, tx, at<SMALL>(uw, idx), at<SMALL>(vw, idx),
+                               at<SMALL>(dzdx, idx), at<SMALL>(dzdy, idx), row, c);
             const T pn0 = A[fy][tx];
             const T pn = T(0.5) * (pn0 + B[fy][tx]) + hdt * F2;
             A[fy][tx] = pn;   // stage-1 reads of A ended at the last barrier
@@ -409,7 +428,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
             // crossing zero, or a node lit by this step's ignition
             T ti = INF, told = INF;
             if (pn <= T(0) || tig[k] < INF) {
-                told = tign[idx];
+                told = at<SMALL>(tign, idx);
                 ti = told;
                 if (is_inf(ti)) ti = tig[k];
                 if (pn0 > T(0) && pn <= T(0) && is_inf(ti))
@@ -417,8 +436,8 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
             }
             C[fy][tx] = pn >= T(0) ? tp : ti;
             if (xr3 && fy >= 3 && fy < a.tile_y + 3) {
-                psi_out[idx] = pn;
-                if (!(ti == told)) tign[idx] = ti;
+                at<SMALL>(psi_out, idx) = pn;
+                if (!(ti == told)) at<SMALL>(tign, idx) = ti;
                 const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
                 if (edge && pn < T(0)) st |= kStBoundary;
                 if (!__builtin_isfinite(pn)) st |= kStNonfinite;
@@ -451,10 +470,10 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         T fs = T(0);
         fl[k] = T(0);
         if (xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi) {
-            const int idx = off0 + fy * nx;
-            const T fo = frac[idx];
-            const int cv = cat[idx];
-            const T *row = tab + (cv < ncm1 ? cv : ncm1) * kLRow;
+            const uint32_t idx = off0 + fy * unx;
+            const T fo = at<SMALL>(frac, idx);
+            const int cv = at<SMALL>(cat, idx);
+            const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
             T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
             mn = vmin(mn, vmin(vmin(A[fy][tx - 1], A[fy][tx]), A[fy][tx + 1]));
             mn = vmin(mn, vmin(vmin(A[fy + 1][tx - 1], A[fy + 1][tx]), A[fy + 1][tx + 1]));
@@ -463,7 +482,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
             const T dF = M<T>::div(fo - Fn, dt);
             fs = dF * row[kLCh];
             fl[k] = dF * row[kLCq];
-            if (!(Fn == fo)) frac[idx] = Fn;
+            if (!(Fn == fo)) at<SMALL>(frac, idx) = Fn;
             if (!__builtin_isfinite(Fn)) st |= kStNonfinite;
         }
         if (fy < FH) B[fy][tx] = fs;
@@ -601,10 +620,23 @@ template <typename T> __global__ void k_to_f64(const T *src, double *dst, int n)
 }
 
 template <typename T, int KR>
+hipError_t step_k_big(const StepArgs &a, const StepBuffers &b, hipStream_t s, size_t dyn,
+                      int grid) {
+    hipLaunchKernelGGL((k_step<T, KR, false>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+                       (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
+                       (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
+                       b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
+    return hipGetLastError();
+}
+
+template <typename T, int KR>
 hipError_t step_k(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     const size_t dyn = (size_t)a.ncat * kLRow * sizeof(T);
     const int grid = a.per_xcd * 8;
-    hipLaunchKernelGGL((k_step<T, KR>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+    const bool small = (uint64_t)a.nx * a.ny * sizeof(T) < ((uint64_t)1 << 32);
+    if (!small)
+        return step_k_big<T, KR>(a, b, s, dyn, grid);
+    hipLaunchKernelGGL((k_step<T, KR, true>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
                        (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
                        (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
                        b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
@@ -619,7 +651,14 @@ hipError_t step_t(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     if (fh <= 20) return step_k<T, 5>(a, b, s);
     if (fh <= 24) return step_k<T, 6>(a, b, s);
     if (fh <= 28) return step_k<T, 7>(a, b, s);
-    return step_k<T, 8>(a, b, s);
+    if (fh <= 32) return step_k<T, 8>(a, b, s);
+    if constexpr (sizeof(T) == 4) {
+        if (fh <= 36) return step_k<T, 9>(a, b, s);
+        if (fh <= 40) return step_k<T, 10>(a, b, s);
+        if (fh <= 44) return step_k<T, 11>(a, b, s);
+        return step_k<T, 12>(a, b, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace

@@ -48,6 +48,9 @@ def workload(name):
         return p, "f32"
     if name == "uniform128":
         return synth.uniform_fire(128), "f64"
+    if name == "ensemble256":
+        return synth.ensemble(ndom=256, side_min=256, side_max=1024, steps=500,
+                              field_dtype=np.float32), "f32"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -59,11 +62,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(name, dtype):
+def pmc_traffic(name, dtype, kernel=KERNEL):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary for this workload, if it was taken on the current kernel
     source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{name}_{dtype}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{dtype}_pmc.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -114,10 +117,12 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="patchy8192",
-                    choices=("patchy8192", "patchy2048", "uniform128"))
+                    choices=("patchy8192", "patchy2048", "uniform128", "ensemble256"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
+    ap.add_argument("--loop-steps", type=int, default=50,
+                    help="ensemble workload: steps of the loop of plain contexts to time")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -152,6 +157,8 @@ def main():
     t = time.perf_counter()
     prob, dtype = workload(args.workload)
     log(f"generated in {time.perf_counter() - t:.1f} s")
+    if args.workload == "ensemble256":
+        return run_ensemble(args, prob, dtype)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     stream = torch.cuda.current_stream()
     fire = F.Fire.from_problem(prob, dtype=tdt)
@@ -199,8 +206,11 @@ def main():
     cells = prob.nx * prob.ny
     value = cells * K / elapsed
     status = fire.status()
+    burning = float((fire.psi < 0).float().mean())
+    q = max(1, K // 10)
     log(f"{K} steps in {elapsed * 1e3:.2f} ms (wall {wall * 1e3:.1f} ms), kernel avg "
-        f"{avg_kernel_s * 1e6:.1f} us, status {status}")
+        f"{avg_kernel_s * 1e6:.1f} us (first tenth {sum(kern_ms[:q]) / q * 1e3:.1f}, last "
+        f"{sum(kern_ms[-q:]) / q * 1e3:.1f}), status {status}, burning {burning:.4f}")
 
     bytes_per_launch = B_ALG[dtype] * cells
     achieved = bytes_per_launch / avg_kernel_s / 1e9
@@ -235,7 +245,134 @@ def main():
                                f"-> {fire.nax}x{fire.nay} atmosphere cells",
                    "nx": prob.nx, "ny": prob.ny, "dt": prob.dt, "sr": prob.sr_x,
                    "wind_fields": len(prob.wind), "wind_period": prob.wind_period,
-                   "tile": list(fire.get_tile()), "status": status},
+                   "tile": list(fire.get_tile()), "status": status,
+                   "burning_frac_end": round(burning, 5)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+ENS_TILES = [(120, 20), (120, 10), (60, 20), (120, 30), (120, 40), (60, 10), (60, 40)]
+
+
+def run_ensemble(args, probs, dtype):
+    """All members in one launch per step (HIP graph replay of fire_ens_step),
+    against a loop of one plain fire_step per member and step."""
+    import numpy as np
+    import torch
+    from paper_1102_1343_amd import fire as F
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    stream = torch.cuda.current_stream()
+    ens = F.FireEnsemble.from_problems(probs, dtype=tdt)
+    u = ens.concat([p.wind[0][0] for p in probs])
+    v = ens.concat([p.wind[0][1] for p in probs])
+    fs, fl = ens.new_flux()
+    dt = probs[0].dt
+    cells = ens.ncells
+    torch.cuda.synchronize()
+    if args.tile:
+        best = tuple(int(x) for x in args.tile.split(","))
+        ens.set_tile(*best)
+    else:
+        log(f"ensemble of {ens.ndom}, {cells} cells resident; autotuning tiles")
+        best = ens.autotune(u, v, dt, ENS_TILES, reps=3)
+    log(f"tile {best}; warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        ens.step(u, v, dt, fs, fl)
+    torch.cuda.synchronize()
+
+    # capture one step; each replay is one step of every member
+    side = torch.cuda.Stream()
+    ens.set_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            ens.step(u, v, dt, fs, fl)
+    ens.set_stream(stream)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(K):
+        ev[k][0].record(stream)
+        graph.replay()
+        ev[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    step_us = [a.elapsed_time(b) * 1e3 for a, b in ev]
+    avg_step_s = sum(step_us) / len(step_us) / 1e6
+    value = cells * K / (total_ms / 1e3)
+    status = ens.status()
+    burning = float((ens.psi < 0).float().mean())
+    q = max(1, K // 10)
+    log(f"{K} graph steps in {total_ms:.2f} ms, avg {avg_step_s * 1e6:.1f} us/step (first "
+        f"tenth {sum(step_us[:q]) / q:.1f}, last {sum(step_us[-q:]) / q:.1f}), "
+        f"{int((status != 0).sum())} members flagged, burning {burning:.4f}")
+    del graph
+
+    # the same members as plain contexts, one fire_step each per step
+    KL = max(1, min(args.loop_steps, K))
+    plain = [F.Fire.from_problem(p, dtype=tdt) for p in probs]
+    pw = [(ens.member(u, k), ens.member(v, k)) for k in range(len(probs))]
+    pf = [g.new_flux() for g in plain]
+    for g, (uu, vv), (a, b) in zip(plain, pw, pf):
+        g.step(uu, vv, dt, a, b)
+    torch.cuda.synchronize()
+    l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    l0.record(stream)
+    for _ in range(KL):
+        for g, (uu, vv), (a, b) in zip(plain, pw, pf):
+            g.step(uu, vv, dt, a, b)
+    l1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = l0.elapsed_time(l1)
+    loop_value = cells * KL / (loop_ms / 1e3)
+    log(f"loop of {len(plain)} plain steps: {loop_ms / KL:.3f} ms/step")
+    for g in plain:
+        g.close()
+
+    bytes_per_launch = B_ALG[dtype] * cells
+    achieved = bytes_per_launch / avg_step_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": pmc_traffic(args.workload, dtype, kernel="k_ens_step"),
+            "kernel": "k_ens_step", "avg_kernel_us": round(avg_step_s * 1e6, 2),
+            "alg_bytes_per_cell_step": B_ALG[dtype],
+            "note": "duration per graph replay (step kernel + one-thread clock kernel)"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (cpu_baseline)")
+        cpu = cpu_baseline(probs[0], dtype, args.cpu_seconds)
+    sides = [p.nx for p in probs]
+    out = {
+        "metric": "fire cell-steps/s",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"ensemble256: {len(probs)} square fire domains, sides "
+                               f"{min(sides)}-{max(sides)} (sum {cells} cells), dx=6 m, "
+                               f"dt={dt} s, refinement 10, one HIP-graph replay per step",
+                   "members": len(probs), "cells": cells, "tile": list(best),
+                   "members_flagged": int((status != 0).sum()),
+                   "burning_frac_end": round(burning, 5)},
+        "ensemble": {"loop_value": loop_value, "loop_steps": KL,
+                     "loop_ms_per_step": loop_ms / KL,
+                     "speedup_vs_loop": value / loop_value},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define FIRE_ABI_VERSION 1
+#define FIRE_ABI_VERSION 2
 
 enum {
     FIRE_OK = 0,
@@ -187,8 +187,8 @@ int fire_ros_eval(fire_ctx *ctx, const uint8_t *cat, const void *un, const void 
                   int64_t n);
 
 /* Tile shape of the fused step kernel: tile_x a multiple of sr_x with
- * tile_x <= 122, tile_y a multiple of sr_y with tile_y <= 26.  Results do not
- * depend on the tile shape. */
+ * tile_x <= 122, tile_y a multiple of sr_y with tile_y <= 42 (FP32) or
+ * <= 26 (FP64).  Results do not depend on the tile shape. */
 int fire_set_tile(fire_ctx *ctx, int32_t tile_x, int32_t tile_y);
 int fire_get_tile(fire_ctx *ctx, int32_t *tile_x, int32_t *tile_y);
 
@@ -200,6 +200,87 @@ int fire_abi_version(void);
 
 /* Releases the context (no device memory is freed: the caller owns it). */
 void fire_destroy(fire_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Ensemble: many independent fire domains of different sizes advanced by one
+ * kernel launch per step (the data-parallel use of Sect. 9: many fire
+ * simulations, each the method of fire_step() unchanged).  Every member
+ * computes exactly what a single-domain context with the same mesh, fuels,
+ * ignitions and parameters computes, bit for bit, whatever the tile shape.
+ *
+ * Members share the fuel table, the parameters, dtype and the refinement
+ * ratio; they differ in nx, ny, dx, dy, terrain, wind and ignitions.  Per-cell
+ * arrays of all members are concatenated: member k's [ny_k][nx_k] block starts
+ * at element cell_off[k]; atmosphere arrays likewise at atm_off[k]
+ * (fire_ens_layout()).  The model time and the index of the current psi
+ * buffer live on the device (advanced by a one-thread kernel after each step),
+ * so fire_ens_step() enqueues the same two kernels every call and may be
+ * captured once in a HIP graph and replayed: each replay is one step.
+ * ---------------------------------------------------------------------- */
+typedef struct fire_ens fire_ens;
+
+/* Element offsets of the members' blocks: cell_off[ndom + 1] into per-cell
+ * arrays and atm_off[ndom + 1] into atmosphere arrays (host arrays written by
+ * the call; the last entry is the total).  All meshes must be valid and share
+ * dtype, sr_x and sr_y; 1 <= ndom <= 65535. */
+int fire_ens_layout(const fire_mesh *meshes, int32_t ndom, int64_t *cell_off, int64_t *atm_off);
+
+/* Bytes of the caller-owned device arena for the ensemble (0 if invalid). */
+size_t fire_ens_state_bytes(const fire_mesh *meshes, int32_t ndom, int32_t ncat);
+
+/*
+ * Create an ensemble and initialise every member as fire_init() does.
+ *   meshes[ndom], cats[ncat], prm : host, copied
+ *   fuel_cat, dzdx, dzdy : device, concatenated per-cell arrays
+ *   ign : host, the members' ignitions one after another, nign[k] of member
+ *         k (0 <= nign[k] <= FIRE_MAX_IGNITIONS); NULL if all are 0
+ *   state : device arena of fire_ens_state_bytes(), 256-byte aligned
+ * Waits for the set-up copies; fuel_cat, dzdx, dzdy and state must stay
+ * valid until fire_ens_destroy().
+ */
+int fire_ens_init(fire_ens **out, const fire_mesh *meshes, int32_t ndom, const fire_fuel *cats,
+                  int32_t ncat, const uint8_t *fuel_cat, const void *dzdx, const void *dzdy,
+                  const fire_ignition *ign, const int32_t *nign, const fire_params *prm,
+                  void *state, size_t state_bytes, void *stream);
+
+/* One step of length dt of every member, winds u, v as concatenated per-cell
+ * arrays, fluxes into concatenated atmosphere arrays.  Never waits; the
+ * boundary condition of a member only sets its status bits (boundary policy
+ * 1 for all members).  Enqueues two kernels and nothing else. */
+int fire_ens_step(fire_ens *e, const void *u, const void *v, double dt, void *flux_sens,
+                  void *flux_lat);
+
+/* Device pointers to the concatenated psi, t_i, F and the model time (waits
+ * for the stream to read the device-side time). */
+int fire_ens_get_state(fire_ens *e, fire_view *out);
+
+/* Sticky FIRE_STATUS_* bits of every member into host status[ndom] (waits). */
+int fire_ens_status(fire_ens *e, int32_t *status);
+
+/* Tile shape (same limits as fire_set_tile()); rebuilds the tile work list
+ * (waits).  Not to be called during graph capture. */
+int fire_ens_set_tile(fire_ens *e, int32_t tile_x, int32_t tile_y);
+int fire_ens_get_tile(fire_ens *e, int32_t *tile_x, int32_t *tile_y);
+
+/* Device scratch bytes fire_ens_autotune() needs (a snapshot of the state). */
+size_t fire_ens_tune_bytes(fire_ens *e);
+
+/*
+ * Times reps steps for each candidate tile shape cand[2*i], cand[2*i+1]
+ * (i < ncand) with the given inputs, keeps the fastest (written to best[2])
+ * and restores the state, time and status from a snapshot in the caller's
+ * scratch (fire_ens_tune_bytes(), 256-byte aligned), so the ensemble is left
+ * as before the call except for the tile shape.  The flux buffers are
+ * overwritten.  Waits.
+ */
+int fire_ens_autotune(fire_ens *e, const void *u, const void *v, double dt, void *flux_sens,
+                      void *flux_lat, const int32_t *cand, int32_t ncand, int32_t reps,
+                      void *scratch, size_t scratch_bytes, int32_t *best);
+
+int fire_ens_set_stream(fire_ens *e, void *stream);
+
+/* Releases the ensemble handle (host memory only). */
+void fire_ens_destroy(fire_ens *e);
 
 #ifdef __cplusplus
 }

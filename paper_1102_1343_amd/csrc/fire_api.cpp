@@ -19,7 +19,7 @@ struct fire_ctx {
     const uint8_t *cat;
     const void *dzdx, *dzdy;
     char *arena;
-    size_t off_coef, off_fuel, off_status, off_psi[2], off_tign, off_frac;
+    size_t off_coef, off_fuel, off_ign, off_status, off_psi[2], off_tign, off_frac;
     int cur;               // index of the current psi buffer
     double t;              // model time of the current state
     hipStream_t stream;
@@ -27,13 +27,7 @@ struct fire_ctx {
     int stopped;           // boundary reached under the stop policy
 };
 
-namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-size_t esize(const fire_mesh *m) { return m->dtype == FIRE_F64 ? 8 : 4; }
+namespace fire {
 
 bool mesh_ok(const fire_mesh *m) {
     if (!m) return false;
@@ -45,8 +39,65 @@ bool mesh_ok(const fire_mesh *m) {
     return m->dtype == FIRE_F32 || m->dtype == FIRE_F64;
 }
 
+bool params_ok(const fire_params *prm) {
+    if (!prm) return false;
+    if (!(prm->viscosity >= 0.0) || !std::isfinite(prm->viscosity)) return false;
+    if (!(prm->wind_cap > 0.0) || !(prm->ros_cap > 0.0) || !std::isfinite(prm->t0)) return false;
+    if (prm->guard_width < 0 || (prm->boundary_policy != 0 && prm->boundary_policy != 1) ||
+        (prm->viscosity_mode != 0 && prm->viscosity_mode != 1))
+        return false;
+    return true;
+}
+
+bool fuels_ok(const fire_fuel *cats, int ncat) {
+    if (!cats || ncat < 1 || ncat > 256) return false;
+    for (int k = 0; k < ncat; k++) {
+        const fire_fuel &f = cats[k];
+        if (!(f.ros_mult >= 0.0)) return false;
+        if (!(f.tf > 0.0) && !(f.weight > 0.0)) return false;
+        if (!f.ichap && !(f.fgi > 0.0 && f.fueldepthm > 0.0 && f.savr > 0.0 && f.fuelmce > 0.0 &&
+                          f.fueldens > 0.0 && f.se > 0.0 && f.fuelmc_g >= 0.0))
+            return false;
+    }
+    return true;
+}
+
+bool ignitions_ok(const fire_ignition *ign, int nign) {
+    if (nign < 0 || nign > FIRE_MAX_IGNITIONS || (nign > 0 && !ign)) return false;
+    for (int g = 0; g < nign; g++) {
+        const fire_ignition &r = ign[g];
+        if (!(r.ros > 0.0) || !(r.radius >= 0.0) || !std::isfinite(r.radius) ||
+            !std::isfinite(r.t_start))
+            return false;
+        if ((r.vx != 0.0 || r.vy != 0.0) && !(r.t_end >= r.t_start)) return false;
+    }
+    return true;
+}
+
+// default tile: widest multiple of sr_x that fits the frame, and the
+// tallest multiple of sr_y up to 20 rows (26 when sr_y does not divide 20)
+void default_tile(const fire_mesh *m, int *tx, int *ty) {
+    *tx = (kTileXMax / m->sr_x) * m->sr_x;
+    int best = 0;
+    for (int h = m->sr_y; h <= kTileYMax; h += m->sr_y)
+        if (h <= 20) best = h;
+    if (best == 0) best = (kTileYMax / m->sr_y) * m->sr_y;
+    *ty = best;
+}
+
+bool tile_ok(const fire_mesh *m, int tile_x, int tile_y) {
+    const int ymax = m->dtype == FIRE_F64 ? kTileYMax64 : kTileYMax;
+    if (tile_x < 1 || tile_x > kTileXMax || tile_x % m->sr_x != 0) return false;
+    if (tile_y < 1 || tile_y > ymax || tile_y % m->sr_y != 0) return false;
+    return true;
+}
+
+}  // namespace fire
+
+namespace {
+
 struct Layout {
-    size_t coef, fuel, status, psi0, psi1, tign, frac, total;
+    size_t coef, fuel, ign, status, psi0, psi1, tign, frac, total;
 };
 
 Layout layout(const fire_mesh *m, int ncat) {
@@ -57,6 +108,8 @@ Layout layout(const fire_mesh *m, int ncat) {
     o = align_up(o + (size_t)ncat * kNCoef * e);
     L.fuel = o;
     o = align_up(o + (size_t)ncat * sizeof(fire_fuel));
+    L.ign = o;
+    o = align_up(o + FIRE_MAX_IGNITIONS * sizeof(fire_ignition));
     L.status = o;
     o = align_up(o + 64);
     L.psi0 = o;
@@ -69,17 +122,6 @@ Layout layout(const fire_mesh *m, int ncat) {
     o = align_up(o + n * e);
     L.total = o;
     return L;
-}
-
-// default tile: widest multiple of sr_x that fits the frame, and the
-// tallest multiple of sr_y up to 20 rows (26 when sr_y does not divide 20)
-void default_tile(const fire_mesh *m, int *tx, int *ty) {
-    *tx = (kTileXMax / m->sr_x) * m->sr_x;
-    int best = 0;
-    for (int h = m->sr_y; h <= kTileYMax; h += m->sr_y)
-        if (h <= 20) best = h;
-    if (best == 0) best = (kTileYMax / m->sr_y) * m->sr_y;
-    *ty = best;
 }
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP; }
@@ -116,33 +158,12 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
               size_t state_bytes, void *stream) {
     if (!out) return FIRE_ERR_ARG;
     *out = nullptr;
-    if (!mesh_ok(mesh) || !cats || ncat < 1 || ncat > 256 || !fuel_cat || !dzdx || !dzdy ||
-        !prm || !state || nign < 0 || nign > FIRE_MAX_IGNITIONS || (nign > 0 && !ign))
+    if (!mesh_ok(mesh) || !fuels_ok(cats, ncat) || !fuel_cat || !dzdx || !dzdy ||
+        !params_ok(prm) || !state || !ignitions_ok(ign, nign))
         return FIRE_ERR_ARG;
     if (((uintptr_t)state % kAlign) != 0) return FIRE_ERR_ARG;
     const Layout L = layout(mesh, ncat);
     if (state_bytes < L.total) return FIRE_ERR_ARG;
-    if (!(prm->viscosity >= 0.0) || !std::isfinite(prm->viscosity)) return FIRE_ERR_ARG;
-    if (!(prm->wind_cap > 0.0) || !(prm->ros_cap > 0.0) || !std::isfinite(prm->t0))
-        return FIRE_ERR_ARG;
-    if (prm->guard_width < 0 || (prm->boundary_policy != 0 && prm->boundary_policy != 1) ||
-        (prm->viscosity_mode != 0 && prm->viscosity_mode != 1))
-        return FIRE_ERR_ARG;
-    for (int k = 0; k < ncat; k++) {
-        const fire_fuel &f = cats[k];
-        if (!(f.ros_mult >= 0.0)) return FIRE_ERR_ARG;
-        if (!(f.tf > 0.0) && !(f.weight > 0.0)) return FIRE_ERR_ARG;
-        if (!f.ichap && !(f.fgi > 0.0 && f.fueldepthm > 0.0 && f.savr > 0.0 && f.fuelmce > 0.0 &&
-                          f.fueldens > 0.0 && f.se > 0.0 && f.fuelmc_g >= 0.0))
-            return FIRE_ERR_ARG;
-    }
-    for (int g = 0; g < nign; g++) {
-        const fire_ignition &r = ign[g];
-        if (!(r.ros > 0.0) || !(r.radius >= 0.0) || !std::isfinite(r.radius) ||
-            !std::isfinite(r.t_start))
-            return FIRE_ERR_ARG;
-        if ((r.vx != 0.0 || r.vy != 0.0) && !(r.t_end >= r.t_start)) return FIRE_ERR_ARG;
-    }
 
     fire_ctx *c = new (std::nothrow) fire_ctx();
     if (!c) return FIRE_ERR_OOM;
@@ -157,6 +178,7 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
     c->arena = (char *)state;
     c->off_coef = L.coef;
     c->off_fuel = L.fuel;
+    c->off_ign = L.ign;
     c->off_status = L.status;
     c->off_psi[0] = L.psi0;
     c->off_psi[1] = L.psi1;
@@ -172,6 +194,9 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
     // space); the copy is synchronous because cats is pageable host memory
     hipError_t e = hipMemcpyAsync(state_ptr(c, L.fuel), cats, sizeof(fire_fuel) * ncat,
                                   hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && nign > 0)
+        e = hipMemcpyAsync(state_ptr(c, L.ign), ign, sizeof(fire_ignition) * nign,
+                           hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess)
         e = launch_coef(mesh->dtype, (const fire_fuel *)state_ptr(c, L.fuel), ncat, prm->wind_cap,
@@ -225,7 +250,6 @@ int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_s
     a.dt = dt;
     a.eps = c->prm.viscosity;
     a.ros_cap = c->prm.ros_cap;
-    for (int g = 0; g < c->nign; g++) a.ign[g] = c->ign[g];
 
     StepBuffers b;
     b.psi_in = state_ptr(c, c->off_psi[c->cur]);
@@ -241,6 +265,11 @@ int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_s
     b.fsens = flux_sens;
     b.flat = flux_lat;
     b.status = (int *)state_ptr(c, c->off_status);
+    b.ign = (const fire_ignition *)state_ptr(c, c->off_ign);
+    b.ncells = (size_t)m.nx * m.ny;
+    b.ens_doms = nullptr;
+    b.ens_tile_dom = nullptr;
+    b.ens_clock = nullptr;
 
     hipError_t e = launch_step(m.dtype, a, b, c->stream);
     if (e != hipSuccess) return FIRE_ERR_HIP;
@@ -325,10 +354,7 @@ int fire_ros_eval(fire_ctx *c, const uint8_t *cat, const void *un, const void *t
 }
 
 int fire_set_tile(fire_ctx *c, int32_t tile_x, int32_t tile_y) {
-    if (!c) return FIRE_ERR_ARG;
-    if (tile_x < 1 || tile_x > kTileXMax || tile_x % c->mesh.sr_x != 0) return FIRE_ERR_ARG;
-    const int ymax = c->mesh.dtype == FIRE_F64 ? kTileYMax64 : kTileYMax;
-    if (tile_y < 1 || tile_y > ymax || tile_y % c->mesh.sr_y != 0) return FIRE_ERR_ARG;
+    if (!c || !tile_ok(&c->mesh, tile_x, tile_y)) return FIRE_ERR_ARG;
     c->tile_x = tile_x;
     c->tile_y = tile_y;
     return FIRE_OK;

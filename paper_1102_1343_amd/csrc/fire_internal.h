@@ -31,17 +31,35 @@ enum { kS0, kR0, kB, kC, kD, kE, kM, kTf, kCh, kCq, kNCoef };
 constexpr int kStBoundary = FIRE_STATUS_BOUNDARY;
 constexpr int kStNonfinite = FIRE_STATUS_NONFINITE;
 
+// Per-launch arguments.  For one domain the domain fields describe it; for an
+// ensemble they are overwritten per tile from the domain table.
 struct StepArgs {
     int32_t nx, ny;
     int32_t tile_x, tile_y;
-    int32_t tiles_x, ntiles, per_xcd;
+    int32_t tiles_x, ntiles, per_xcd;   // ntiles: total tiles of the launch
     int32_t sr_x, sr_y, nax, nay;
     int32_t ncat, guard, visc_mode, nign, pad;
     double dx, dy;
     double rdx, rdy;     // 1/dx, 1/dy
-    double t, dt;
+    double t, dt;        // t unused by the ensemble kernel (device time)
     double eps, ros_cap;
-    fire_ignition ign[FIRE_MAX_IGNITIONS];
+};
+
+// One member of an ensemble (device table row).
+struct EnsDomain {
+    int32_t nx, ny, tiles_x, tile0;     // tile0: first work-list tile of the domain
+    int32_t nax, nay, nign, pad;
+    double dx, dy, rdx, rdy;
+    int64_t cell_off, atm_off;          // element offsets into the concatenated arrays
+};
+
+// Device-side clock of an ensemble: model time and which psi buffer holds
+// the current state, so that a step enqueues the same launches every time
+// (graph capture).
+struct EnsClock {
+    double t;
+    int32_t cur;
+    int32_t pad;
 };
 
 struct StepBuffers {
@@ -54,6 +72,12 @@ struct StepBuffers {
     const void *coef;
     void *fsens, *flat;
     int *status;
+    const fire_ignition *ign;           // device ignition records: one domain's, or
+                                        // FIRE_MAX_IGNITIONS per ensemble member
+    size_t ncells;                      // cells in the (concatenated) arrays
+    const EnsDomain *ens_doms;          // non-null for an ensemble launch; then
+    const int32_t *ens_tile_dom;        // psi_in / psi_out are the two buffers and
+    const EnsClock *ens_clock;          // the clock says which is current
 };
 
 // launchers (return hipError_t of the launch)
@@ -66,5 +90,17 @@ hipError_t launch_ros_eval(int dtype, const void *coef, int ncat, double ros_cap
                            const uint8_t *cat, const void *un, const void *tn, void *S,
                            int64_t n, hipStream_t s);
 hipError_t launch_coef_to_f64(int dtype, const void *coef, double *out, int n, hipStream_t s);
+hipError_t launch_advance_clock(EnsClock *c, double dt, hipStream_t s);
+
+// ---- host helpers shared by the single-domain and ensemble ABI layers
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline size_t esize(const fire_mesh *m) { return m->dtype == FIRE_F64 ? 8 : 4; }
+bool mesh_ok(const fire_mesh *m);
+bool params_ok(const fire_params *p);
+bool fuels_ok(const fire_fuel *cats, int ncat);
+bool ignitions_ok(const fire_ignition *ign, int nign);
+void default_tile(const fire_mesh *m, int *tx, int *ty);
+bool tile_ok(const fire_mesh *m, int tile_x, int tile_y);
 
 }  // namespace fire

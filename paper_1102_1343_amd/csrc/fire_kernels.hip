@@ -265,11 +265,12 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 // LDS frames: A holds psi^n, then psi^{n+1}, then the latent flux; B holds
 // psi*, then the sensible flux; C holds the node ignition times t^.
 template <typename T, int KR, bool SMALL>
-__global__ void __launch_bounds__(kBlock)
-k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
-       const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
-       const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
-       T *__restrict__ fsens, T *__restrict__ flat, int *status) {
+__device__ __forceinline__ void
+step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double tnow,
+          const fire_ignition *ign, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
+          const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
+          const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
+          T *__restrict__ fsens, T *__restrict__ flat, int *status) {
     constexpr int FHM = kNR * KR;
     __shared__ T A[FHM][kFW];
     __shared__ T B[FHM][kFW];
@@ -277,11 +278,6 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     extern __shared__ __attribute__((aligned(32))) double dyn_smem[];
     T *tab = reinterpret_cast<T *>(dyn_smem);
 
-    // XCD-aware tile order: work-group b runs on XCD b % 8; give each XCD a
-    // contiguous range of row-major tiles so halo rows stay in its L2.
-    const int bid = blockIdx.x;
-    const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
-    if (tile >= a.ntiles) return;
     const int tyi = tile / a.tiles_x;
     const int txi = tile - tyi * a.tiles_x;
     const int x0 = txi * a.tile_x, y0 = tyi * a.tile_y;
@@ -299,8 +295,10 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     const int yhi = ny - y0 + kHalo < FH ? ny - y0 + kHalo : FH;
     // a frame that lies inside the domain has no ghost nodes
     const bool interior = x0 >= kHalo && x0 + a.tile_x + kHalo <= nx && ylo == 0 && yhi == FH;
-    // element index of frame row 0 (mod 2^32; in-domain indices are < 2^31)
-    const uint32_t off0 = (uint32_t)((y0 - kHalo) * nx + gx);
+    // element index of frame row 0 (mod 2^32), plus the domain's first
+    // element cbase when the arrays are concatenated; in-domain indices are
+    // below 2^32 (2^31 for one domain)
+    const uint32_t off0 = cbase + (uint32_t)((y0 - kHalo) * nx + gx);
     const uint32_t unx = (uint32_t)nx;
 
     for (int i = tid; i < a.ncat; i += kBlock) {
@@ -327,8 +325,8 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     c.visc_mode = a.visc_mode;
     const T dt = T(a.dt);
     const T hdt = T(0.5 * a.dt);
-    const T t = T(a.t);
-    const T tp = T(a.t + a.dt);
+    const T t = T(tnow);
+    const T tp = T(tnow + a.dt);
     const T INF = M<T>::inf();
     const int ncm1 = a.ncat - 1;
 
@@ -351,7 +349,7 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
         const double xg = ((double)gx + 0.5) * a.dx;
         for (int g = 0; g < a.nign; g++) {
             IgnGeo<T> geo;
-            if (!ign_setup<T>(a.ign[g], a.t, geo)) continue;
+            if (!ign_setup<T>(ign[g], tnow, geo)) continue;
             const T px = T(xg - geo.ax);
 #pragma unroll
             for (int k = 0; k < KR; k++) {
@@ -532,6 +530,95 @@ k_step(const StepArgs a, const T *__restrict__ psi_in, T *__restrict__ psi_out, 
     }
 }
 
+
+// One fire domain: work-group b takes tile (b % 8) * per_xcd + b / 8, so each
+// of the eight XCDs sweeps a contiguous band of row-major tiles and halo rows
+// stay in its L2.
+// Minimum waves per SIMD asked of the register allocator.  The FP32 frame of
+// the default 120 x 20 tile (KR = 7, 43 KiB of LDS) allows three work-groups
+// of 8 waves per CU, i.e. 6 waves per SIMD, which needs <= 80 VGPRs; the
+// ensemble kernel lands a few registers above that unless asked.  Elsewhere
+// the same request would force scratch spills, so nothing is asked (1).
+template <typename T, int KR> constexpr int waves_per_simd() {
+    return (sizeof(T) == 4 && KR == 7) ? 6 : 1;
+}
+
+template <typename T, int KR, bool SMALL>
+__global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
+k_step(const StepArgs a, const fire_ignition *ign, const T *__restrict__ psi_in,
+       T *__restrict__ psi_out, T *tign, T *frac, const T *__restrict__ uw,
+       const T *__restrict__ vw, const T *__restrict__ dzdx, const T *__restrict__ dzdy,
+       const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
+       T *__restrict__ flat, int *status) {
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (tile >= a.ntiles) return;
+    step_tile<T, KR, SMALL>(a, tile, 0u, a.t, ign, psi_in, psi_out, tign, frac, uw, vw, dzdx,
+                            dzdy, cat, coef, fsens, flat, status);
+}
+
+// An ensemble of domains in one launch: the tiles of all domains form one
+// work list (domain-major), mapped onto the XCDs like a single domain; each
+// work-group finds its domain, whose arrays sit at that domain's offsets in
+// the concatenated buffers.  The model time is read from device memory so a
+// step can be captured once and replayed.
+template <typename T, int KR, bool SMALL>
+__global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
+k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
+           const int32_t *__restrict__ tile_dom, const EnsClock *__restrict__ clock,
+           const fire_ignition *__restrict__ ign_all, T *psi_a,
+           T *psi_b, T *tign, T *frac, const T *__restrict__ uw, const T *__restrict__ vw,
+           const T *__restrict__ dzdx, const T *__restrict__ dzdy,
+           const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
+           T *__restrict__ flat, int *status) {
+    const int bid = blockIdx.x;
+    const int g = (bid & 7) * common.per_xcd + (bid >> 3);
+    if (g >= common.ntiles) return;
+    // one member per work-group: keep its index (and so every field of its
+    // table row) in scalar registers
+    const int di = __builtin_amdgcn_readfirstlane(tile_dom[g]);
+    const EnsDomain &d = doms[di];
+    StepArgs a = common;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.tiles_x = d.tiles_x;
+    a.nax = d.nax;
+    a.nay = d.nay;
+    a.nign = d.nign;
+    a.dx = d.dx;
+    a.dy = d.dy;
+    a.rdx = d.rdx;
+    a.rdy = d.rdy;
+    // a member's ignitions: FIRE_MAX_IGNITIONS records from ign_all + di * 8,
+    // indexed from the kernel argument so the loads stay global-memory loads
+    const fire_ignition *ign = ign_all + (size_t)di * FIRE_MAX_IGNITIONS;
+    const double tnow = clock->t;
+    const bool flip = clock->cur != 0;
+    const T *pin = flip ? psi_b : psi_a;
+    T *pout = flip ? psi_a : psi_b;
+    const size_t a0 = (size_t)d.atm_off;
+    if (SMALL) {
+        // the member's first element goes into the 32-bit element index, so
+        // the array bases stay the launch's (no per-member 64-bit pointers)
+        step_tile<T, KR, SMALL>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, ign, pin, pout,
+                                tign, frac, uw, vw, dzdx, dzdy, cat, coef, fsens + a0,
+                                flat + a0, status + di);
+    } else {
+        const size_t c0 = (size_t)d.cell_off;
+        step_tile<T, KR, SMALL>(a, g - d.tile0, 0u, tnow, ign, pin + c0, pout + c0, tign + c0,
+                                frac + c0, uw + c0, vw + c0, dzdx + c0, dzdy + c0, cat + c0,
+                                coef, fsens + a0, flat + a0, status + di);
+    }
+}
+
+// Advances an ensemble's device clock after its step kernel (stream order).
+__global__ void k_advance_clock(EnsClock *c, double dt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->t += dt;
+        c->cur ^= 1;
+    }
+}
+
 // ---------------------------------------------------------------- init kernels
 
 template <typename T>
@@ -619,28 +706,30 @@ template <typename T> __global__ void k_to_f64(const T *src, double *dst, int n)
     if (i < n) dst[i] = (double)src[i];
 }
 
-template <typename T, int KR>
-hipError_t step_k_big(const StepArgs &a, const StepBuffers &b, hipStream_t s, size_t dyn,
-                      int grid) {
-    hipLaunchKernelGGL((k_step<T, KR, false>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
-                       (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
-                       (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
-                       b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
+template <typename T, int KR, bool SMALL>
+hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
+    const size_t dyn = (size_t)a.ncat * kLRow * sizeof(T);
+    const int grid = a.per_xcd * 8;
+    if (b.ens_doms) {
+        hipLaunchKernelGGL((k_ens_step<T, KR, SMALL>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+                           b.ens_doms, b.ens_tile_dom, b.ens_clock, b.ign, (T *)b.psi_in,
+                           (T *)b.psi_out, (T *)b.tign, (T *)b.frac, (const T *)b.u,
+                           (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy, b.cat,
+                           (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
+    } else {
+        hipLaunchKernelGGL((k_step<T, KR, SMALL>), dim3(grid), dim3(kFW, kNR), dyn, s, a, b.ign,
+                           (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
+                           (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
+                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int KR>
 hipError_t step_k(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
-    const size_t dyn = (size_t)a.ncat * kLRow * sizeof(T);
-    const int grid = a.per_xcd * 8;
-    const bool small = (uint64_t)a.nx * a.ny * sizeof(T) < ((uint64_t)1 << 32);
-    if (!small)
-        return step_k_big<T, KR>(a, b, s, dyn, grid);
-    hipLaunchKernelGGL((k_step<T, KR, true>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
-                       (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
-                       (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
-                       b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
-    return hipGetLastError();
+    // 32-bit byte offsets when every (concatenated) array is below 4 GiB
+    const bool small = (uint64_t)b.ncells * sizeof(T) < ((uint64_t)1 << 32);
+    return small ? launch_one<T, KR, true>(a, b, s) : launch_one<T, KR, false>(a, b, s);
 }
 
 // frame height tile_y + 6 <= 4 KR
@@ -665,6 +754,11 @@ hipError_t step_t(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
 
 hipError_t launch_step(int dtype, const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     return dtype == FIRE_F64 ? step_t<double>(a, b, s) : step_t<float>(a, b, s);
+}
+
+hipError_t launch_advance_clock(EnsClock *c, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(64), 0, s, c, dt);
+    return hipGetLastError();
 }
 
 hipError_t launch_coef(int dtype, const fire_fuel *fuels_dev, int ncat, double wind_cap,

@@ -89,6 +89,25 @@ def lib():
         L.fire_strerror.restype = C.c_char_p
         L.fire_destroy.argtypes = [vp]
         L.fire_destroy.restype = None
+        i64p, i32p = P(C.c_int64), P(C.c_int32)
+        L.fire_ens_layout.argtypes = [P(fire_mesh), C.c_int32, i64p, i64p]
+        L.fire_ens_state_bytes.argtypes = [P(fire_mesh), C.c_int32, C.c_int32]
+        L.fire_ens_state_bytes.restype = C.c_size_t
+        L.fire_ens_init.argtypes = [P(vp), P(fire_mesh), C.c_int32, P(fire_fuel), C.c_int32, vp,
+                                    vp, vp, P(fire_ignition), i32p, P(fire_params), vp,
+                                    C.c_size_t, vp]
+        L.fire_ens_step.argtypes = [vp, vp, vp, C.c_double, vp, vp]
+        L.fire_ens_get_state.argtypes = [vp, P(fire_view)]
+        L.fire_ens_status.argtypes = [vp, i32p]
+        L.fire_ens_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
+        L.fire_ens_get_tile.argtypes = [vp, i32p, i32p]
+        L.fire_ens_tune_bytes.argtypes = [vp]
+        L.fire_ens_tune_bytes.restype = C.c_size_t
+        L.fire_ens_autotune.argtypes = [vp, vp, vp, C.c_double, vp, vp, i32p, C.c_int32,
+                                        C.c_int32, vp, C.c_size_t, i32p]
+        L.fire_ens_set_stream.argtypes = [vp, vp]
+        L.fire_ens_destroy.argtypes = [vp]
+        L.fire_ens_destroy.restype = None
         _lib = L
     return _lib
 
@@ -276,6 +295,11 @@ class Fire:
     def set_tile(self, tile_x, tile_y):
         _check(lib().fire_set_tile(self._ctx, int(tile_x), int(tile_y)), "fire_set_tile")
 
+    def set_stream(self, stream):
+        """Enqueue later calls on ``stream`` (a torch.cuda.Stream)."""
+        self._stream = stream
+        _check(lib().fire_set_stream(self._ctx, _stream_handle(stream)), "fire_set_stream")
+
     def get_tile(self):
         a, b = C.c_int32(), C.c_int32()
         _check(lib().fire_get_tile(self._ctx, C.byref(a), C.byref(b)), "fire_get_tile")
@@ -285,6 +309,186 @@ class Fire:
         if getattr(self, "_ctx", None):
             lib().fire_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FireEnsemble:
+    """Many fire domains of different sizes stepped by one launch per step.
+
+    ``members`` are ``synth.Problem``-like objects (nx, ny, dx, dy, sr_x,
+    sr_y, cat, dzdx, dzdy, ignitions); all share ``fuels`` and the
+    parameters.  Per-cell arrays are concatenated 1-D tensors: member k owns
+    elements ``cell_off[k]:cell_off[k+1]`` (row-major [ny_k, nx_k]);
+    atmosphere arrays likewise with ``atm_off``.
+    """
+
+    def __init__(self, members, fuels, dtype=torch.float32, device="cuda", viscosity=0.4,
+                 psi_init=0.0, wind_cap=30.0, ros_cap=math.inf, t0=0.0, guard_width=1,
+                 viscosity_mode=0, stream=None):
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.ndom = len(members)
+        fd = FIRE_F64 if dtype == torch.float64 else FIRE_F32
+        self.meshes = (fire_mesh * self.ndom)()
+        for k, m in enumerate(members):
+            self.meshes[k] = fire_mesh(int(m.nx), int(m.ny), float(m.dx), float(m.dy),
+                                       int(m.sr_x), int(m.sr_y), fd, 0)
+        self.shapes = [(int(m.ny), int(m.nx)) for m in members]
+        self.atm_shapes = [(-(-int(m.ny) // int(m.sr_y)), -(-int(m.nx) // int(m.sr_x)))
+                           for m in members]
+        co = (C.c_int64 * (self.ndom + 1))()
+        ao = (C.c_int64 * (self.ndom + 1))()
+        _check(lib().fire_ens_layout(self.meshes, self.ndom, co, ao), "fire_ens_layout")
+        self.cell_off = np.array(co[:], dtype=np.int64)
+        self.atm_off = np.array(ao[:], dtype=np.int64)
+        self.ncat = len(fuels)
+        self.cat = self.concat([m.cat for m in members], torch.uint8)
+        if int(self.cat.max()) >= self.ncat:
+            raise ValueError("fuel category map holds a value >= number of fuels")
+        self.dzdx = self.concat([m.dzdx for m in members])
+        self.dzdy = self.concat([m.dzdy for m in members])
+        igs, nign = [], (C.c_int32 * self.ndom)()
+        for k, m in enumerate(members):
+            if len(m.ignitions) > MAX_IGNITIONS:
+                raise ValueError(f"member {k}: at most {MAX_IGNITIONS} ignitions")
+            igs += list(m.ignitions)
+            nign[k] = len(m.ignitions)
+        ign_c = _ign_array(igs)
+        self.params = fire_params(float(viscosity), float(psi_init), float(wind_cap),
+                                  float(ros_cap), float(t0), int(guard_width), 1,
+                                  int(viscosity_mode), 0)
+        nbytes = lib().fire_ens_state_bytes(self.meshes, self.ndom, self.ncat)
+        if nbytes == 0:
+            raise FireError(-1, "fire_ens_state_bytes")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._base = self.arena.data_ptr() + (-self.arena.data_ptr()) % 256
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib().fire_ens_init(C.byref(h), self.meshes, self.ndom, _fuel_array(fuels),
+                                   self.ncat, C.c_void_p(self.cat.data_ptr()),
+                                   C.c_void_p(self.dzdx.data_ptr()),
+                                   C.c_void_p(self.dzdy.data_ptr()), ign_c, nign,
+                                   C.byref(self.params), C.c_void_p(self._base), nbytes,
+                                   _stream_handle(stream)), "fire_ens_init")
+        self._h = h
+
+    @classmethod
+    def from_problems(cls, probs, dtype=torch.float32, device="cuda", **kw):
+        p = dict(probs[0].params)
+        p.update(kw)
+        return cls(probs, probs[0].fuels, dtype=dtype, device=device,
+                   **{k: v for k, v in p.items() if k in (
+                       "viscosity", "psi_init", "wind_cap", "ros_cap", "t0", "guard_width",
+                       "viscosity_mode", "stream")})
+
+    @property
+    def ncells(self):
+        return int(self.cell_off[-1])
+
+    def concat(self, arrays, dtype=None):
+        """Concatenate per-member [ny_k, nx_k] arrays into one device tensor."""
+        dtype = dtype or self.dtype
+        parts = []
+        for k, a in enumerate(arrays):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            if tuple(t.shape) != self.shapes[k]:
+                raise ValueError(f"member {k}: expected shape {self.shapes[k]}, "
+                                 f"got {tuple(t.shape)}")
+            parts.append(t.reshape(-1).to(device=self.device, dtype=dtype))
+        return torch.cat(parts).contiguous()
+
+    def member(self, flat, k, atm=False):
+        """View of member k's block of a concatenated array."""
+        off, shp = (self.atm_off, self.atm_shapes) if atm else (self.cell_off, self.shapes)
+        return flat[int(off[k]):int(off[k + 1])].view(shp[k])
+
+    def new_flux(self):
+        n = int(self.atm_off[-1])
+        z = lambda: torch.empty(n, dtype=self.dtype, device=self.device)
+        return z(), z()
+
+    def step(self, u, v, dt, flux_sens=None, flux_lat=None):
+        if flux_sens is None or flux_lat is None:
+            flux_sens, flux_lat = self.new_flux()
+        for t in (u, v):
+            if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != self.ncells:
+                raise ValueError("wind must be contiguous concatenated tensors of the fire dtype")
+        _check(lib().fire_ens_step(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
+                                   float(dt), C.c_void_p(flux_sens.data_ptr()),
+                                   C.c_void_p(flux_lat.data_ptr())), "fire_ens_step")
+        return flux_sens, flux_lat
+
+    def _view(self):
+        vw = fire_view()
+        _check(lib().fire_ens_get_state(self._h, C.byref(vw)), "fire_ens_get_state")
+        return vw
+
+    def _slice(self, ptr):
+        off = ptr - self.arena.data_ptr()
+        es = 8 if self.dtype == torch.float64 else 4
+        return self.arena[off:off + self.ncells * es].view(self.dtype)
+
+    @property
+    def psi(self):
+        return self._slice(self._view().psi)
+
+    @property
+    def tign(self):
+        return self._slice(self._view().tign)
+
+    @property
+    def frac(self):
+        return self._slice(self._view().frac)
+
+    @property
+    def t(self):
+        return self._view().t
+
+    def status(self) -> np.ndarray:
+        out = (C.c_int32 * self.ndom)()
+        _check(lib().fire_ens_status(self._h, out), "fire_ens_status")
+        return np.array(out[:], dtype=np.int32)
+
+    def set_tile(self, tile_x, tile_y):
+        _check(lib().fire_ens_set_tile(self._h, int(tile_x), int(tile_y)), "fire_ens_set_tile")
+
+    def set_stream(self, stream):
+        """Enqueue later calls on ``stream`` (a torch.cuda.Stream)."""
+        self._stream = stream
+        _check(lib().fire_ens_set_stream(self._h, _stream_handle(stream)), "fire_ens_set_stream")
+
+    def get_tile(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().fire_ens_get_tile(self._h, C.byref(a), C.byref(b)), "fire_ens_get_tile")
+        return a.value, b.value
+
+    def autotune(self, u, v, dt, candidates, reps=5):
+        """Time each (tile_x, tile_y) candidate, keep the fastest; the state is
+        left as it was.  Returns the chosen shape."""
+        nb = lib().fire_ens_tune_bytes(self._h)
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        base = scratch.data_ptr() + (-scratch.data_ptr()) % 256
+        cand = (C.c_int32 * (2 * len(candidates)))(*[int(x) for c in candidates for x in c])
+        best = (C.c_int32 * 2)()
+        fs, fl = self.new_flux()
+        _check(lib().fire_ens_autotune(self._h, C.c_void_p(u.data_ptr()),
+                                       C.c_void_p(v.data_ptr()), float(dt),
+                                       C.c_void_p(fs.data_ptr()), C.c_void_p(fl.data_ptr()),
+                                       cand, len(candidates), int(reps), C.c_void_p(base), nb,
+                                       best), "fire_ens_autotune")
+        return best[0], best[1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fire_ens_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

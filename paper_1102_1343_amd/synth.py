@@ -301,3 +301,35 @@ def window(prob: Problem, i0: int, j0: int, w: int, h: int) -> Problem:
                    c(prob.cat), c(prob.dzdx), c(prob.dzdy), ign, prob.dt, prob.steps,
                    [(c(u), c(v)) for (u, v) in prob.wind], prob.wind_period, dict(prob.params),
                    f"{prob.name}[{j0}:{j0 + h},{i0}:{i0 + w}]")
+
+
+def ensemble(ndom=256, side_min=256, side_max=1024, steps=500, dt=0.25, seed=SEED,
+             field_dtype=np.float64) -> list:
+    """Ensemble workload: ``ndom`` square domains with side uniform integer in
+    [side_min, side_max], dx = 6 m, each built with the patchy-fire generators
+    from a seed of its own (256 Voronoi fuel patches, 8 hills, 16-mode Fourier
+    wind, 4 line ignitions); its wind amplitude scaled by U[0.8, 1.2] and
+    rotated by U[-15, 15] degrees, its ignition endpoints jittered by up to 3
+    cells.  All members share the 13-category fuel table of the base seed and
+    the patchy-fire parameters; one wind field per member."""
+    rng = np.random.default_rng([seed, 77])
+    fuels = random_fuels(np.random.default_rng(seed))
+    sides = rng.integers(side_min, side_max + 1, ndom)
+    amp = rng.uniform(0.8, 1.2, ndom)
+    rot = rng.uniform(-15.0, 15.0, ndom)
+    dx = 6.0
+    out = []
+    for k in range(ndom):
+        n = int(sides[k])
+        r = np.random.default_rng([seed, 2000 + k])
+        cat = voronoi_categories(r, n, n)
+        gzx, gzy = hills_gradient(r, n, n, dx, dx, dtype=field_dtype)
+        ign = line_ignitions(r, n, n, dx, dx, jitter_cells=3.0)
+        wind = fourier_wind(r, n, n, dx, dx, amp_scale=float(amp[k]), rotate_deg=float(rot[k]),
+                            dtype=field_dtype)
+        out.append(Problem(n, n, dx, dx, 10, 10, [dict(f) for f in fuels], cat, gzx, gzy, ign,
+                           dt, steps, [wind], 0,
+                           dict(viscosity=0.4, viscosity_mode=0, ros_cap=6.0,
+                                boundary_policy=1, guard_width=1),
+                           name=f"ens{k}_{n}"))
+    return out

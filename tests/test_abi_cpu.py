@@ -67,7 +67,7 @@ def test_state_bytes_and_errors_without_gpu(lib):
         assert lib.fire_state_bytes(C.byref(bad), 13) == 0
     assert lib.fire_state_bytes(C.byref(m), 0) == 0
     assert lib.fire_state_bytes(C.byref(m), 257) == 0
-    assert lib.fire_abi_version() == 1
+    assert lib.fire_abi_version() == 2
     assert lib.fire_strerror(-4) == b"fire reached the domain boundary guard ring"
     assert lib.fire_strerror(0) == b"ok"
     # argument errors are reported before any device work
@@ -76,3 +76,37 @@ def test_state_bytes_and_errors_without_gpu(lib):
                          C.c_size_t(0), None) == -1
     assert lib.fire_step(None, None, None, C.c_double(0.5), None, None, None) == -1
     assert lib.fire_status(None) == -1
+
+
+def test_ensemble_layout_and_errors_without_gpu(lib):
+    from paper_1102_1343_amd import fire as F
+    lib.fire_ens_state_bytes.restype = C.c_size_t
+    sides = [(37, 50), (256, 300), (10, 10), (1001, 7)]
+    ms = (F.fire_mesh * len(sides))(*[F.fire_mesh(nx, ny, 6.0, 6.0, 10, 10, F.FIRE_F32, 0)
+                                      for nx, ny in sides])
+    co = (C.c_int64 * (len(sides) + 1))()
+    ao = (C.c_int64 * (len(sides) + 1))()
+    assert lib.fire_ens_layout(ms, len(sides), co, ao) == 0
+    cells = [0]
+    atm = [0]
+    for nx, ny in sides:
+        cells.append(cells[-1] + nx * ny)
+        atm.append(atm[-1] + -(-nx // 10) * -(-ny // 10))
+    assert list(co) == cells and list(ao) == atm
+    nb = lib.fire_ens_state_bytes(ms, len(sides), 13)
+    assert nb >= 16 * cells[-1] + 2 * atm[-1]
+    assert lib.fire_ens_state_bytes(ms, len(sides), 0) == 0
+    # members must share dtype and refinement ratio
+    for field, val in (("dtype", F.FIRE_F64), ("sr_x", 5), ("sr_y", 2)):
+        bad = (F.fire_mesh * 2)(ms[0], ms[1])
+        setattr(bad[1], field, val)
+        assert lib.fire_ens_layout(bad, 2, co, ao) == -1
+        assert lib.fire_ens_state_bytes(bad, 2, 13) == 0
+    assert lib.fire_ens_layout(ms, 0, co, ao) == -1
+    assert lib.fire_ens_layout(ms, 70000, co, ao) == -1
+    h = C.c_void_p()
+    nign = (C.c_int32 * len(sides))()
+    assert lib.fire_ens_init(C.byref(h), ms, len(sides), None, 0, None, None, None, None, nign,
+                             None, None, C.c_size_t(0), None) == -1
+    assert lib.fire_ens_step(None, None, None, C.c_double(0.5), None, None) == -1
+    assert lib.fire_ens_status(None, None) == -1

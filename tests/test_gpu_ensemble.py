@@ -1,0 +1,183 @@
+"""Batched ensemble of uneven domains through the C ABI (needs a GPU).
+
+Each member of an ensemble must compute exactly what a single-domain context
+computes on its inputs: psi, t_i, F and both fluxes are compared bit for bit
+against one plain context per member, for several tile shapes, after
+autotuning, and under HIP-graph replay.  Members are also checked against
+the FP64 oracle to the FP64 bar.
+"""
+from __future__ import annotations
+
+import types
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1102_1343_amd import fire as F
+from paper_1102_1343_amd import synth
+
+from parity import Compare64, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _members(ndom, lo, hi, seed, dtype):
+    fd = np.float32 if dtype == torch.float32 else np.float64
+    return synth.ensemble(ndom=ndom, side_min=lo, side_max=hi, steps=20, seed=seed,
+                          field_dtype=fd)
+
+
+def _ens_wind(ens, probs):
+    u = ens.concat([p.wind[0][0] for p in probs])
+    v = ens.concat([p.wind[0][1] for p in probs])
+    return u, v
+
+
+def _plain_run(probs, dtype, steps):
+    """Members one by one through plain contexts: final psi, t_i, F, last fluxes."""
+    out = []
+    for p in probs:
+        g = F.Fire.from_problem(p, dtype=dtype)
+        u = torch.from_numpy(np.ascontiguousarray(p.wind[0][0])).to("cuda", dtype)
+        v = torch.from_numpy(np.ascontiguousarray(p.wind[0][1])).to("cuda", dtype)
+        fs, fl = g.new_flux()
+        for _ in range(steps):
+            g.step(u, v, p.dt, fs, fl)
+        torch.cuda.synchronize()
+        out.append((g.psi.clone(), g.tign.clone(), g.frac.clone(), fs.clone(), fl.clone(),
+                    g.status(), g.t))
+        g.close()
+    return out
+
+
+def _assert_members_equal(ens, ref, fs, fl, what):
+    st = ens.status()
+    for k, (psi, tig, frac, rfs, rfl, rst, rt) in enumerate(ref):
+        for name, a, b in (("psi", ens.member(ens.psi, k), psi),
+                           ("tign", ens.member(ens.tign, k), tig),
+                           ("frac", ens.member(ens.frac, k), frac),
+                           ("flux_sens", ens.member(fs, k, atm=True), rfs),
+                           ("flux_lat", ens.member(fl, k, atm=True), rfl)):
+            # bitwise: compare the raw bits (NaN-safe, -0 vs +0 distinguished)
+            ia = a.contiguous().view(torch.int32 if a.dtype == torch.float32 else torch.int64)
+            ib = b.contiguous().view(torch.int32 if b.dtype == torch.float32 else torch.int64)
+            nbad = int((ia != ib).sum())
+            assert nbad == 0, f"{what}: member {k} {name}: {nbad} elements differ"
+        assert st[k] == rst, f"{what}: member {k} status {st[k]} != {rst}"
+    assert ens.t == ref[0][6]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_ensemble_members_bitwise_equal_plain(dtype):
+    probs = _members(9, 24, 170, 101, dtype)
+    steps = 44          # ignitions start within the first 10 s
+    _log(f"ensemble {[p.nx for p in probs]} {dtype}")
+    ref = _plain_run(probs, dtype, steps)
+    tiles = [None, (60, 10), (120, 30) if dtype == torch.float32 else (120, 20), (10, 10)]
+    for tile in tiles:
+        ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
+        if tile:
+            ens.set_tile(*tile)
+        u, v = _ens_wind(ens, probs)
+        fs, fl = ens.new_flux()
+        for _ in range(steps):
+            ens.step(u, v, probs[0].dt, fs, fl)
+        torch.cuda.synchronize()
+        _assert_members_equal(ens, ref, fs, fl, f"tile {ens.get_tile()}")
+        ens.close()
+    assert sum(np.isfinite(host(r[1])).sum() for r in ref) > 100
+
+
+def test_ensemble_fp64_parity_oracle():
+    probs = _members(5, 20, 120, 202, torch.float64)
+    ens = F.FireEnsemble.from_problems(probs, dtype=torch.float64)
+    u, v = _ens_wind(ens, probs)
+    orc = [oracle.OracleFire(p) for p in probs]
+    cmps = [Compare64(p) for p in probs]
+    fs, fl = ens.new_flux()
+    for step in range(44):     # ignitions start within the first 10 s
+        prevs = [(o.psi.copy(), o.t) for o in orc]
+        ens.step(u, v, probs[0].dt, fs, fl)
+        torch.cuda.synchronize()
+        for k, (p, o, c) in enumerate(zip(probs, orc, cmps)):
+            fs_o, fl_o = o.step(*p.wind[0], p.dt)
+            view = types.SimpleNamespace(psi=ens.member(ens.psi, k), tign=ens.member(ens.tign, k),
+                                         frac=ens.member(ens.frac, k))
+            c.step(view, o, ens.member(fs, k, atm=True), ens.member(fl, k, atm=True), fs_o, fl_o,
+                   *prevs[k])
+    assert sum(np.isfinite(o.tign).sum() for o in orc) > 50
+
+
+def test_ensemble_autotune_restores_state():
+    dtype = torch.float32
+    probs = _members(12, 40, 260, 303, dtype)
+    steps = 12
+    ref = _plain_run(probs, dtype, steps)
+    ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
+    u, v = _ens_wind(ens, probs)
+    fs, fl = ens.new_flux()
+    for _ in range(steps // 2):
+        ens.step(u, v, probs[0].dt, fs, fl)
+    t_before = ens.t
+    best = ens.autotune(u, v, probs[0].dt, [(120, 20), (60, 20), (120, 10), (120, 40)], reps=2)
+    _log(f"autotune picked {best}")
+    assert best in [(120, 20), (60, 20), (120, 10), (120, 40)]
+    assert ens.get_tile() == best
+    assert ens.t == t_before
+    for _ in range(steps - steps // 2):
+        ens.step(u, v, probs[0].dt, fs, fl)
+    torch.cuda.synchronize()
+    _assert_members_equal(ens, ref, fs, fl, "after autotune")
+
+
+def test_ensemble_graph_replay():
+    dtype = torch.float32
+    probs = _members(7, 30, 200, 404, dtype)
+    steps = 10
+    ref = _plain_run(probs, dtype, steps)
+    ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
+    u, v = _ens_wind(ens, probs)
+    fs, fl = ens.new_flux()
+    ens.step(u, v, probs[0].dt, fs, fl)    # one eager step, then graph replays
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    ens.set_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            ens.step(u, v, probs[0].dt, fs, fl)
+    ens.set_stream(torch.cuda.current_stream())
+    # capture does not execute: the ensemble is still after one step
+    torch.cuda.synchronize()
+    for k in range(steps - 1):
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = float(ens.psi.sum())          # eager work between replays
+    torch.cuda.synchronize()
+    # the model time is kept on the device and advances with every replay
+    assert ens.t == ref[0][6]
+    _assert_members_equal(ens, ref, fs, fl, "graph replay")
+    del graph
+
+
+def test_ensemble_status_per_member():
+    dtype = torch.float64
+    probs = _members(4, 40, 60, 505, dtype)
+    # member 2: an instant ignition touching the guard ring
+    p = probs[2]
+    p.ignitions = [synth.ignition(1.5 * p.dx, 0.5 * p.ny * p.dy, t_start=0.0, radius=3 * p.dx,
+                                  ros=float("inf"))]
+    ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
+    u, v = _ens_wind(ens, probs)
+    fs, fl = ens.new_flux()
+    for _ in range(3):
+        ens.step(u, v, p.dt, fs, fl)
+    st = ens.status()
+    assert st[2] & F.STATUS_BOUNDARY
+    assert all(st[k] == 0 for k in (0, 1, 3)), st

@@ -62,17 +62,20 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(name, dtype, kernel=KERNEL):
+def pmc_traffic(name, dtype, tile, kernel=KERNEL):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary for this workload, if it was taken on the current kernel
-    source; else None."""
+    source with the same tile shape; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{dtype}_pmc.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_source_hash():
+    t = re.search(r"tile:\s*(\d+)x(\d+)", txt)
+    if not m or not b or not t or m.group(1) != kernel_source_hash():
+        return None
+    if (int(t.group(1)), int(t.group(2))) != tuple(tile):
         return None
     return float(b.group(1))
 
@@ -114,7 +117,8 @@ def cpu_baseline(prob, dtype, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's own step count, at most 1000)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="patchy8192",
                     choices=("patchy8192", "patchy2048", "uniform128", "ensemble256"))
@@ -157,6 +161,8 @@ def main():
     t = time.perf_counter()
     prob, dtype = workload(args.workload)
     log(f"generated in {time.perf_counter() - t:.1f} s")
+    if args.steps is None:
+        args.steps = min(1000, (prob[0] if isinstance(prob, list) else prob).steps)
     if args.workload == "ensemble256":
         return run_ensemble(args, prob, dtype)
     tdt = torch.float32 if dtype == "f32" else torch.float64
@@ -214,7 +220,7 @@ def main():
 
     bytes_per_launch = B_ALG[dtype] * cells
     achieved = bytes_per_launch / avg_kernel_s / 1e9
-    traffic = pmc_traffic(args.workload, dtype)
+    traffic = pmc_traffic(args.workload, dtype, fire.get_tile())
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": KERNEL, "avg_kernel_us": round(avg_kernel_s * 1e6, 2),
@@ -252,6 +258,40 @@ def main():
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def cpu_baseline_members(probs, dtype, seconds):
+    """The FP64 oracle on the ensemble's members in order, each for the
+    workload's steps from t = 0, until ``seconds`` of wall time have passed
+    (the last member stops at a whole step)."""
+    import numpy as np
+    import oracle
+
+    cells_steps = 0
+    done = []
+    t0 = time.perf_counter()
+    el = 0.0
+    for p in probs:
+        q = p.cast(np.float32) if dtype == "f32" else p
+        o = oracle.OracleFire(q)
+        k = 0
+        while k < p.steps:
+            o.step(*q.wind_at(k), q.dt)
+            k += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+        cells_steps += p.nx * p.ny * k
+        done.append((p.nx, k))
+        if el >= seconds:
+            break
+    full = sum(1 for _, k in done if k == probs[0].steps)
+    return {"value": cells_steps / el, "unit": "cell-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle on the first {len(done)} members in order (sides "
+                      f"{', '.join(str(n) for n, _ in done)}), {full} of them for all "
+                      f"{probs[0].steps} steps from t=0, the last for {done[-1][1]}; "
+                      f"{el:.1f} s wall"}
 
 
 ENS_TILES = [(120, 20), (120, 10), (60, 20), (120, 30), (120, 40), (60, 10), (60, 40)]
@@ -342,14 +382,15 @@ def run_ensemble(args, probs, dtype):
     achieved = bytes_per_launch / avg_step_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": pmc_traffic(args.workload, dtype, kernel="k_ens_step"),
+            "traffic": pmc_traffic(args.workload, dtype, best, kernel="k_ens_step"),
             "kernel": "k_ens_step", "avg_kernel_us": round(avg_step_s * 1e6, 2),
             "alg_bytes_per_cell_step": B_ALG[dtype],
             "note": "duration per graph replay (step kernel + one-thread clock kernel)"}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (cpu_baseline)")
-        cpu = cpu_baseline(probs[0], dtype, args.cpu_seconds)
+        cpu = cpu_baseline_members(probs, dtype, args.cpu_seconds)
+        log(f"oracle {cpu['value']:.3e} cell-steps/s on {cpu['cores']} threads")
     sides = [p.nx for p in probs]
     out = {
         "metric": "fire cell-steps/s",

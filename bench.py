@@ -48,6 +48,8 @@ def workload(name):
         return p, "f32"
     if name == "uniform128":
         return synth.uniform_fire(128), "f64"
+    if name == "adjoint1024":
+        return synth.adjoint_case(n=1024, steps=500, field_dtype=np.float32), "f32"
     if name == "ensemble256":
         return synth.ensemble(ndom=256, side_min=256, side_max=1024, steps=500,
                               field_dtype=np.float32), "f32"
@@ -121,10 +123,13 @@ def main():
                     help="timed steps (default: the workload's own step count, at most 1000)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="patchy8192",
-                    choices=("patchy8192", "patchy2048", "uniform128", "ensemble256"))
+                    choices=("patchy8192", "patchy2048", "uniform128", "ensemble256",
+                             "adjoint1024"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
+    ap.add_argument("--every", type=int, default=50,
+                    help="adjoint workload: checkpoint interval (steps)")
     ap.add_argument("--loop-steps", type=int, default=50,
                     help="ensemble workload: steps of the loop of plain contexts to time")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -161,6 +166,8 @@ def main():
     t = time.perf_counter()
     prob, dtype = workload(args.workload)
     log(f"generated in {time.perf_counter() - t:.1f} s")
+    if args.workload == "adjoint1024":
+        return run_adjoint(args, *prob, dtype)
     if args.steps is None:
         args.steps = min(1000, (prob[0] if isinstance(prob, list) else prob).steps)
     if args.workload == "ensemble256":
@@ -292,6 +299,102 @@ def cpu_baseline_members(probs, dtype, seconds):
                       f"{', '.join(str(n) for n, _ in done)}), {full} of them for all "
                       f"{probs[0].steps} steps from t=0, the last for {done[-1][1]}; "
                       f"{el:.1f} s wall"}
+
+
+def run_adjoint(args, prob, pert, dtype):
+    """Cost of the hand-written adjoint: a run of `steps` fire steps under
+    one wind, then the backward pass of L = 1/2 sum (F_end - F_target)^2 to
+    the per-cell wind, the category multipliers and the ignition shifts,
+    against the same run as plain fire_step calls."""
+    import numpy as np
+    import torch
+    from paper_1102_1343_amd import fire as F
+
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    K = args.steps or prob.steps
+    stream = torch.cuda.current_stream()
+    u = torch.from_numpy(np.ascontiguousarray(prob.wind[0][0])).to("cuda", tdt)
+    v = torch.from_numpy(np.ascontiguousarray(prob.wind[0][1])).to("cuda", tdt)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # target: the perturbed run
+    fuels = [dict(f, ros_mult=float(m)) for f, m in zip(prob.fuels, pert["mult"])]
+    tgt = F.Fire(prob.nx, prob.ny, prob.dx, prob.dy, prob.sr_x, prob.sr_y, fuels, prob.cat,
+                 prob.dzdx, prob.dzdy, F.shifted_ignitions(prob.ignitions, pert["shift"]),
+                 dtype=tdt, **{k: prob.params[k] for k in ("viscosity", "ros_cap",
+                                                            "boundary_policy")})
+    fs, fl = tgt.new_flux()
+    us, vs = u * pert["wind_scale"], v * pert["wind_scale"]
+    for _ in range(K):
+        tgt.step(us, vs, prob.dt, fs, fl)
+    target = tgt.frac.clone()
+    tgt.close()
+
+    # plain forward
+    plain = F.Fire.from_problem(prob, dtype=tdt)
+    fs, fl = plain.new_flux()
+    plain.step(u, v, prob.dt, fs, fl)      # warm-up launch
+    plain.close()
+    plain = F.Fire.from_problem(prob, dtype=tdt)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(K):
+        plain.step(u, v, prob.dt, fs, fl)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    F_plain = plain.frac.clone()
+    plain.close()
+
+    # recording forward + backward
+    fire = F.Fire.from_problem(prob, dtype=tdt)
+    adj = F.FireAdjoint(fire, K, args.every)
+    torch.cuda.synchronize()
+    e0, e1, e2 = ev(), ev(), ev()
+    e0.record(stream)
+    Fend = adj.forward(u, v, prob.dt)
+    e1.record(stream)
+    dF = (Fend - target).contiguous()
+    gu, gv, gm, gs = adj.backward(dF)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    rec_ms, bwd_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    same = bool(torch.equal(Fend, F_plain))
+    loss = 0.5 * float(((Fend - target).double() ** 2).sum())
+    log(f"{K} steps: plain forward {fwd_ms:.1f} ms, recording forward {rec_ms:.1f} ms, "
+        f"backward {bwd_ms:.1f} ms; loss {loss:.4e}; F_end equal to the plain run: {same}")
+    out = {
+        "metric": "adjoint/forward cost",
+        "value": bwd_ms / fwd_ms,
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": 1,
+        "ms_per_step": bwd_ms / K,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"adjoint1024: {prob.nx}x{prob.ny} fire mesh, dx={prob.dx} m, "
+                               f"{len(prob.fuels)} fuels, 2 instant circular ignitions, "
+                               f"dt={prob.dt} s, {K} steps, checkpoint every {args.every}; "
+                               "loss 1/2 sum (F_end - F_target)^2",
+                   "nx": prob.nx, "ny": prob.ny, "every": args.every},
+        "adjoint": {"forward_ms": fwd_ms, "recording_forward_ms": rec_ms, "backward_ms": bwd_ms,
+                    "forward_and_backward_over_forward": (rec_ms + bwd_ms) / fwd_ms,
+                    "loss": loss, "F_end_equals_plain_run": same,
+                    "grad_norms": {"u": float(gu.double().norm()), "v": float(gv.double().norm()),
+                                   "mult": float(np.linalg.norm(gm)),
+                                   "shift": float(np.linalg.norm(gs))}},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 ENS_TILES = [(120, 20), (120, 10), (60, 20), (120, 30), (120, 40), (60, 10), (60, 40)]

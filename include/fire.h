@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define FIRE_ABI_VERSION 2
+#define FIRE_ABI_VERSION 3
 
 enum {
     FIRE_OK = 0,
@@ -281,6 +281,50 @@ int fire_ens_set_stream(fire_ens *e, void *stream);
 
 /* Releases the ensemble handle (host memory only). */
 void fire_ens_destroy(fire_ens *e);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of a run of fire steps.  A differentiable run
+ * advances a context nsteps steps of length dt under one surface wind
+ * (u, v), keeping psi every `every` steps; the backward pass takes dL/dF
+ * of the fuel fraction after the last step and returns
+ *   dL/du, dL/dv   per cell, summed over the steps;
+ *   dL/dm_k        per fuel category, m_k the spread multiplier
+ *                  (fire_fuel.ros_mult, Eq. 3);
+ *   dL/d(shift)    per ignition, the translation of its start point and
+ *                  segment (the centre of a point ignition, Sect. 4.4).
+ * Derivatives are those of the discrete step along the branches the forward
+ * took (Godunov side, spread-rate clamps and cap, ghost formula, ignition
+ * minimum, crossing step of Eq. 14, signs in Eqs. 15-19).  Results do not
+ * depend on `every` (segments are replayed bit for bit).
+ * ---------------------------------------------------------------------- */
+typedef struct fire_adj fire_adj;
+
+/* Bytes of caller-owned device scratch for a differentiable run of nsteps
+ * steps with a checkpoint every `every` steps: about
+ * (nsteps/every + every + 24) x nx x ny elements.  0 if invalid. */
+size_t fire_adj_bytes(const fire_mesh *mesh, int32_t ncat, int32_t nsteps, int32_t every);
+
+/* Attach to a context (which must outlive the handle); scratch is device
+ * memory of fire_adj_bytes(), 256-byte aligned. */
+int fire_adj_init(fire_adj **out, fire_ctx *ctx, int32_t nsteps, int32_t every, void *scratch,
+                  size_t scratch_bytes);
+
+/* Run the context nsteps steps from its current state with wind u, v
+ * (device [ny][nx], kept by pointer until the backward pass) and step dt,
+ * recording what the backward pass needs.  The context ends after the last
+ * step; F there is the run's output.  Returns fire_step's errors. */
+int fire_adj_forward(fire_adj *a, const void *u, const void *v, double dt);
+
+/* Backward pass for dF = dL/dF_end (device [ny][nx]): writes grad_u, grad_v
+ * (device [ny][nx], context dtype), grad_mult (host double[ncat]) and, if not
+ * NULL, grad_shift (host double[2 nign], x then y per ignition).  The context
+ * must not have been stepped since fire_adj_forward (FIRE_ERR_STATE).
+ * Waits for the stream. */
+int fire_adj_backward(fire_adj *a, const void *dF, void *grad_u, void *grad_v,
+                      double *grad_mult, double *grad_shift);
+
+/* Releases the handle (host memory only). */
+void fire_adj_destroy(fire_adj *a);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,960 @@
+// Reverse mode (adjoint) of the fire-mesh time step, and its C ABI.
+//
+// A differentiable run advances a context N steps with one surface wind
+// (u, v) and step dt, keeping psi every K steps and, per node, the step in
+// which its ignition time was set.  The backward pass takes dL/dF of the
+// final fuel fraction and returns dL/du, dL/dv (per cell, summed over the
+// steps), dL/dm_k (per-category spread multipliers) and dL/d(shift) of each
+// ignition (translation of its segment or point).  Each segment of K steps
+// is replayed with the forward kernel (bit-identical psi), then its steps are
+// reversed one by one:
+//
+//   psi' = ignite(psi^n)                       (Sect. 4.4, min over ignitions)
+//   psi* = psi' + dt F(G psi')                 (Eq. 11, stage 1)
+//   psi^{n+1} = (psi' + psi*)/2 + dt/2 F(G psi*)   (stage 2)
+//   t_i = t + psi' dt / (psi' - psi^{n+1})     (Eq. 14, nodes crossing in the step)
+//   F_end = quadrature of Eqs. (15)-(19) on psi^N and t^
+//
+// with G the boundary extrapolation of Sect. 4.1 and F the right-hand side
+// of Eqs. (12)-(13) with the spread rate of Eq. (3).  The discrete map is
+// piecewise smooth; every branch (Godunov side, clamps and caps of the spread
+// rate, ghost formula, ignition minimum, crossing step, sub-cell signs) is
+// taken where the forward took it, and the derivative is that of the branch.
+//
+// The reverse kernels work on ghost-extended arrays ((nx+2) x (ny+2) nodes,
+// one extrapolated ring) so that the stencil transposes need no boundary
+// cases: a cell writes its five weighted partials, every extended node
+// gathers the ones aimed at it in a fixed order, and the transpose of G
+// moves ghost adjoints onto the interior nodes they were extrapolated from.
+// Gradients accumulate per cell in double and are reduced in a fixed order:
+// results are bitwise reproducible and independent of K.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fire_device.h"
+
+namespace fire {
+namespace {
+
+using namespace dev;
+
+constexpr int kAB = 256;          // threads per block of the adjoint kernels
+constexpr int kShift = 2 * FIRE_MAX_IGNITIONS;
+
+struct AdjArgs {
+    int32_t nx, ny, ncat, nign, visc_mode, pad;
+    double dx, dy, rdx, rdy, eps, cap, t, dt;
+};
+
+__device__ __forceinline__ int ext_idx(const AdjArgs &a, int x, int y) {
+    return (y + 1) * (a.nx + 2) + (x + 1);
+}
+
+template <typename T> __device__ __forceinline__ void load_row(const T *coef, int cv, int ncat,
+                                                               T *row) {
+    const int k = cv < ncat - 1 ? cv : ncat - 1;
+    make_row(coef + k * kNCoef, row);
+}
+
+// d ghost(p, q) / d(p, q): ghost = 2p - q when p >= q, else q.
+template <typename T> __device__ __forceinline__ void dghost(T p, T q, T &dp, T &dq) {
+    if (p >= q) {
+        dp = T(2);
+        dq = T(-1);
+    } else {
+        dp = T(0);
+        dq = T(1);
+    }
+}
+
+// Right-hand side of Eq. (12) at a node and its derivatives with respect to
+// the five stencil values, the wind components and the category multiplier.
+// The forward value is computed exactly as rhs5 does.
+template <typename T> struct RhsGrad {
+    T F, dc, dw, de, ds, dn, du, dv, dm;
+};
+
+template <typename T>
+__device__ RhsGrad<T> rhs5_grad(T pc, T pw, T pe, T ps, T pn, T u, T v, T gzx, T gzy,
+                                const T *row, const T *g, const Consts<T> &c) {
+    RhsGrad<T> r;
+    const T dmx = (pc - pw) * c.rdx, dpx = (pe - pc) * c.rdx;
+    const T dmy = (pc - ps) * c.rdy, dpy = (pn - pc) * c.rdy;
+    const T ax = vmax(dmx, T(0)), bx = vmin(dpx, T(0));
+    const T ay = vmax(dmy, T(0)), by = vmin(dpy, T(0));
+    const bool selx = ax * ax >= bx * bx, sely = ay * ay >= by * by;
+    const T gx2 = vmax(ax * ax, bx * bx), gy2 = vmax(ay * ay, by * by);
+    const T up = M<T>::sqrt(gx2 + gy2);
+    const T cx = (pe - pw) * c.rdx, cy = (pn - ps) * c.rdy;
+    const T cn2 = cx * cx + cy * cy;
+    const T inv = cn2 > T(0) ? M<T>::rsqrt(cn2) : T(0);
+    const T nx = cx * inv, ny = cy * inv;
+    const T un = u * nx + v * ny, tn = gzx * nx + gzy * ny;
+    // spread rate (ros_row) and its pieces
+    const T e = row[kLE], b = row[kLB];
+    const T U = vmin(vmax(un, T(0)), e);
+    const T gg = vmax(tn, T(0));
+    const T Ub = M<T>::powp(U, b);
+    const T s = row[kLR0] + row[kLC] * Ub + row[kLD] * (gg * gg);
+    const T S1 = vmax(s, row[kLS0]);
+    const T S = vmin(S1, c.cap);
+    const T lap = (dpx - dmx) + (dpy - dmy);
+    const T visc = c.visc_mode == 0 ? c.eps * S * lap : c.eps * lap;
+    r.F = visc - S * up;
+
+    // dS/d(un), dS/d(tn), dS/dm along the branch taken
+    const bool live = S1 < c.cap;
+    const bool in_s = s >= row[kLS0];
+    const T dS_dun = (live && in_s && un > T(0) && un < e && U > T(0))
+                         ? row[kLC] * b * M<T>::div(Ub, U) : T(0);
+    const T dS_dtn = (live && in_s && tn > T(0)) ? T(2) * row[kLD] * gg : T(0);
+    const T dS_dm = live ? (in_s ? g[kR0] + g[kC] * Ub + g[kD] * (gg * gg) : g[kS0]) : T(0);
+    // through the unit normal n = (cx, cy)/|.|
+    const T Snx = dS_dun * u + dS_dtn * gzx, Sny = dS_dun * v + dS_dtn * gzy;
+    T dS_dcx = T(0), dS_dcy = T(0);
+    if (cn2 > T(0)) {
+        dS_dcx = inv * ny * (ny * Snx - nx * Sny);
+        dS_dcy = inv * nx * (nx * Sny - ny * Snx);
+    }
+    // Godunov magnitude
+    T Uxm = T(0), Uxp = T(0), Uym = T(0), Uyp = T(0);
+    if (up > T(0)) {
+        const T iu = M<T>::div(T(1), up);
+        if (selx) Uxm = ax * iu; else Uxp = bx * iu;
+        if (sely) Uym = ay * iu; else Uyp = by * iu;
+    }
+    const T dF_dS = (c.visc_mode == 0 ? c.eps * lap : T(0)) - up;
+    const T kl = c.visc_mode == 0 ? c.eps * S : c.eps;
+    // d/d(pc, pw, pe, ps, pn) of up, lap and S
+    const T up_c = c.rdx * (Uxm - Uxp) + c.rdy * (Uym - Uyp);
+    const T up_w = -c.rdx * Uxm, up_e = c.rdx * Uxp, up_s = -c.rdy * Uym, up_n = c.rdy * Uyp;
+    const T lp_c = T(-2) * (c.rdx + c.rdy);
+    r.dc = kl * lp_c - S * up_c;
+    r.dw = dF_dS * (-c.rdx * dS_dcx) + kl * c.rdx - S * up_w;
+    r.de = dF_dS * (c.rdx * dS_dcx) + kl * c.rdx - S * up_e;
+    r.ds = dF_dS * (-c.rdy * dS_dcy) + kl * c.rdy - S * up_s;
+    r.dn = dF_dS * (c.rdy * dS_dcy) + kl * c.rdy - S * up_n;
+    r.du = dF_dS * dS_dun * nx;
+    r.dv = dF_dS * dS_dun * ny;
+    r.dm = dF_dS * dS_dm;
+    return r;
+}
+
+// Fuel fraction of one cell (Eqs. 15-19, as cell_fraction computes it) and
+// its derivatives with respect to the nine node values of psi (gp) and of
+// t^ (gq), p[b][a] / q[b][a] with b the row (south to north), a the column.
+template <typename T>
+__device__ void cell_fraction_grad(const T p[3][3], const T q[3][3], T tp, T rTf, T gp[3][3],
+                                   T gq[3][3]) {
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) gp[b][a] = gq[b][a] = T(0);
+    const T pc = p[1][1], qc = q[1][1];
+#pragma unroll
+    for (int sb = 0; sb < 2; sb++)
+#pragma unroll
+        for (int sa = 0; sa < 2; sa++) {
+            const int ax = 2 * sa, by = 2 * sb;
+            const T pk[4] = {pc, T(0.5) * (pc + p[1][ax]), T(0.5) * (pc + p[by][1]),
+                             T(0.25) * (pc + p[1][ax] + p[by][1] + p[by][ax])};
+            const T qk[4] = {qc, T(0.5) * (qc + q[1][ax]), T(0.5) * (qc + q[by][1]),
+                             T(0.25) * (qc + q[1][ax] + q[by][1] + q[by][ax])};
+            T sum = T(0), asum = T(0), tau = T(0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                sum += pk[k];
+                asum += vabs(pk[k]);
+                tau += pk[k] >= T(0) ? T(0) : (tp - qk[k]);
+            }
+            if (!(asum > T(0))) continue;
+            const T beta = T(0.5) * (T(1) - M<T>::div(sum, asum));
+            const T x = T(0.25) * tau * rTf;
+            const T E = M<T>::one_m_exp_neg(x);
+            const T ex = T(1) - E;   // exp(-x)
+            // F = 1 - 1/4 sum_q beta_q E_q
+            T dpk[4], dqk[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const T sg = pk[k] >= T(0) ? T(1) : T(-1);
+                const T dbeta = T(-0.5) * M<T>::div(asum - sum * sg, asum * asum);
+                dpk[k] = T(-0.25) * dbeta * E;
+                dqk[k] = pk[k] >= T(0) ? T(0) : T(0.0625) * beta * ex * rTf;
+            }
+            // back to the nodes through the bilinear weights
+            gp[1][1] += dpk[0] + T(0.5) * (dpk[1] + dpk[2]) + T(0.25) * dpk[3];
+            gq[1][1] += dqk[0] + T(0.5) * (dqk[1] + dqk[2]) + T(0.25) * dqk[3];
+            gp[1][ax] += T(0.5) * dpk[1] + T(0.25) * dpk[3];
+            gq[1][ax] += T(0.5) * dqk[1] + T(0.25) * dqk[3];
+            gp[by][1] += T(0.5) * dpk[2] + T(0.25) * dpk[3];
+            gq[by][1] += T(0.5) * dqk[2] + T(0.25) * dqk[3];
+            gp[by][ax] += T(0.25) * dpk[3];
+            gq[by][ax] += T(0.25) * dqk[3];
+        }
+}
+
+// Fixed-order sum over a block of kAB threads (thread 0 gets the total).
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kAB / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Adds per-ignition (x, y) contributions of this block into acc[block][2g+c].
+__device__ __forceinline__ void shift_reduce(int g, double cx, double cy, int nign, double *acc,
+                                             double *sh) {
+    const int any = __syncthreads_or(g >= 0);
+    if (!any) return;
+    for (int k = 0; k < nign; k++) {
+        const double sx = block_sum(g == k ? cx : 0.0, sh);
+        const double sy = block_sum(g == k ? cy : 0.0, sh);
+        if (threadIdx.x == 0) {
+            acc[(size_t)blockIdx.x * kShift + 2 * k] += sx;
+            acc[(size_t)blockIdx.x * kShift + 2 * k + 1] += sy;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+// psi' = min(psi, psi_g) over the active ignitions (as the step kernel does),
+// the ignition that set the minimum, and for a node lit in this step the
+// ignition whose arrival time it takes.
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_ignite(const AdjArgs a, const fire_ignition *ign, const T *psi, T *p0, int8_t *sel,
+             int8_t *tsel) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    T p = psi[i];
+    const T pold = p;
+    T tig = M<T>::inf();
+    int sg = -1, tg = -1;
+    const double xg = ((double)x + 0.5) * a.dx, yg = ((double)y + 0.5) * a.dy;
+    for (int g = 0; g < a.nign; g++) {
+        IgnGeo<T> geo;
+        if (!ign_setup<T>(ign[g], a.t, geo)) continue;
+        T arr;
+        const T pg = ign_psi(geo, T(xg - geo.ax), T(yg - geo.ay), arr);
+        if (pg <= T(0) && arr < tig) {
+            tig = arr;
+            tg = g;
+        }
+        if (pg < p) {
+            p = pg;
+            sg = g;
+        }
+    }
+    if (!(pold > T(0) && p <= T(0))) tg = -1;
+    p0[i] = p;
+    sel[i] = (int8_t)sg;
+    tsel[i] = (int8_t)tg;
+}
+
+// Extended copy with the ghost ring of Sect. 4.1 (corners: x extrapolation
+// of the ghost row), as the step kernel fills it.
+template <typename T>
+__global__ void __launch_bounds__(kAB) k_ext(const AdjArgs a, const T *src, T *dst) {
+    const int ex = a.nx + 2, ey = a.ny + 2;
+    const int j = blockIdx.x * kAB + threadIdx.x;
+    if (j >= ex * ey) return;
+    const int x = j % ex - 1, y = j / ex - 1;
+    const bool xin = x >= 0 && x < a.nx, yin = y >= 0 && y < a.ny;
+    const int sx = x < 0 ? 1 : -1, sy = y < 0 ? 1 : -1;
+    const int nx = a.nx;
+    T r;
+    if (xin && yin) {
+        r = src[y * nx + x];
+    } else if (yin) {
+        r = ghost(src[y * nx + x + sx], src[y * nx + x + 2 * sx]);
+    } else if (xin) {
+        r = ghost(src[(y + sy) * nx + x], src[(y + 2 * sy) * nx + x]);
+    } else {
+        const T r1 = ghost(src[(y + sy) * nx + x + sx], src[(y + 2 * sy) * nx + x + sx]);
+        const T r2 = ghost(src[(y + sy) * nx + x + 2 * sx], src[(y + 2 * sy) * nx + x + 2 * sx]);
+        r = ghost(r1, r2);
+    }
+    dst[j] = r;
+}
+
+template <typename T> __device__ __forceinline__ Consts<T> consts(const AdjArgs &a) {
+    Consts<T> c;
+    c.rdx = T(a.rdx);
+    c.rdy = T(a.rdy);
+    c.eps = T(a.eps);
+    c.cap = T(a.cap);
+    c.visc_mode = a.visc_mode;
+    return c;
+}
+
+// psi* = psi' + dt F(G psi') on the interior nodes (stage 1 of Eq. 11).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_stage(const AdjArgs a, const T *E, const T *p0, const T *u, const T *v, const T *gzx,
+            const T *gzy, const uint8_t *cat, const T *coef, T *out) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    alignas(16) T row[kLRow];
+    load_row(coef, cat[i], a.ncat, row);
+    const int c = ext_idx(a, x, y), ex = a.nx + 2;
+    const T F = rhs5(E[c], E[c - 1], E[c + 1], E[c - ex], E[c + ex], u[i], v[i], gzx[i], gzy[i],
+                     row, consts<T>(a));
+    out[i] = p0[i] + T(a.dt) * F;
+}
+
+// Ignition times set in step n (set_step == n): a crossing node (psi' > 0)
+// passes dL/dt_i to psi' and psi^{n+1} through Eq. (14); a node lit by an
+// ignition passes it to that ignition's shift through the arrival time.
+// dL/dt_i is then cleared (before the step t_i was +inf).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_cross(const AdjArgs a, int n, const int32_t *set_step, const T *p0, const T *pn1, T *L1,
+            T *LT, T *LP0, const int8_t *tsel, const fire_ignition *ign, double *acc) {
+    __shared__ double sh[kAB];
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    int g = -1;
+    double cx = 0.0, cy = 0.0;
+    if (i < a.nx * a.ny) {
+        T lp0 = T(0);
+        if (set_step[i] == n) {
+            const T lt = LT[i];
+            LT[i] = T(0);
+            const T p = p0[i], q = pn1[i];
+            if (p > T(0)) {
+                const T D = p - q;
+                const T dt = T(a.dt);
+                const T iD2 = M<T>::div(T(1), D * D);
+                L1[i] += lt * dt * p * iD2;
+                lp0 = -lt * dt * q * iD2;
+            } else if (tsel[i] >= 0 && lt != T(0)) {
+                const int k = tsel[i];
+                IgnGeo<T> geo;
+                if (ign_setup<T>(ign[k], a.t, geo)) {
+                    const int x = i % a.nx, y = i / a.nx;
+                    const T px = T(((double)x + 0.5) * a.dx - geo.ax);
+                    const T py = T(((double)y + 0.5) * a.dy - geo.ay);
+                    T s = (px * geo.ex + py * geo.ey) * geo.invL2;
+                    const bool sfree = s > T(0) && s < T(1);
+                    s = vmin(vmax(s, T(0)), T(1));
+                    const T qx = px - s * geo.ex, qy = py - s * geo.ey;
+                    const T d = M<T>::sqrt(qx * qx + qy * qy);
+                    const T arr = geo.tg + s * geo.lenv + d * geo.invS;
+                    if (arr < geo.t) {
+                        // translation by delta moves the node by -delta relative to the segment
+                        T ax_ = T(0), ay_ = T(0);
+                        if (d > T(0)) {
+                            ax_ = -geo.invS * M<T>::div(qx, d);
+                            ay_ = -geo.invS * M<T>::div(qy, d);
+                        }
+                        if (sfree) {
+                            ax_ -= geo.lenv * geo.ex * geo.invL2;
+                            ay_ -= geo.lenv * geo.ey * geo.invL2;
+                        }
+                        g = k;
+                        cx = (double)(lt * ax_);
+                        cy = (double)(lt * ay_);
+                    }
+                }
+            }
+        }
+        LP0[i] = lp0;
+    }
+    shift_reduce(g, cx, cy, a.nign, acc, sh);
+}
+
+// Cell i of a stage: q = w lambda_i; the five weighted partials of F_i go to
+// D (planes c, w, e, s, n); dL/du, dL/dv, dL/dm accumulate per cell.
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_rhs(const AdjArgs a, const T *E, const T *lam, T w, const T *u, const T *v, const T *gzx,
+          const T *gzy, const uint8_t *cat, const T *coef, T *D, double *gu, double *gv,
+          double *gm) {
+    const int n = a.nx * a.ny;
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= n) return;
+    const T q = w * lam[i];
+    if (q == T(0)) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) D[(size_t)k * n + i] = T(0);
+        return;
+    }
+    const int x = i % a.nx, y = i / a.nx;
+    const int cv = cat[i] < a.ncat - 1 ? cat[i] : a.ncat - 1;
+    alignas(16) T row[kLRow];
+    make_row(coef + cv * kNCoef, row);
+    const int c = ext_idx(a, x, y), ex = a.nx + 2;
+    const RhsGrad<T> r = rhs5_grad(E[c], E[c - 1], E[c + 1], E[c - ex], E[c + ex], u[i], v[i],
+                                   gzx[i], gzy[i], row, coef + cv * kNCoef, consts<T>(a));
+    D[i] = q * r.dc;
+    D[(size_t)n + i] = q * r.dw;
+    D[(size_t)2 * n + i] = q * r.de;
+    D[(size_t)3 * n + i] = q * r.ds;
+    D[(size_t)4 * n + i] = q * r.dn;
+    gu[i] += (double)(q * r.du);
+    gv[i] += (double)(q * r.dv);
+    gm[i] += (double)(q * r.dm);
+}
+
+// Extended node j collects the partials aimed at it, in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(kAB) k_adj_gather(const AdjArgs a, const T *D, T *LE) {
+    const int ex = a.nx + 2, ey = a.ny + 2, n = a.nx * a.ny;
+    const int j = blockIdx.x * kAB + threadIdx.x;
+    if (j >= ex * ey) return;
+    const int x = j % ex - 1, y = j / ex - 1;
+    auto in = [&](int xx, int yy) { return xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny; };
+    T s = T(0);
+    if (in(x, y)) s += D[y * a.nx + x];
+    if (in(x + 1, y)) s += D[(size_t)n + y * a.nx + x + 1];          // east cell's west node
+    if (in(x - 1, y)) s += D[(size_t)2 * n + y * a.nx + x - 1];      // west cell's east node
+    if (in(x, y + 1)) s += D[(size_t)3 * n + (y + 1) * a.nx + x];    // north cell's south node
+    if (in(x, y - 1)) s += D[(size_t)4 * n + (y - 1) * a.nx + x];    // south cell's north node
+    LE[j] = s;
+}
+
+// Corner ghosts (x extrapolation of the ghost row) hand their adjoint to the
+// two ghost-row nodes they came from.  One thread, corners in a fixed order.
+template <typename T> __global__ void k_adj_corners(const AdjArgs a, const T *E, T *LE) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int xs[2] = {-1, a.nx}, ys[2] = {-1, a.ny};
+    for (int cy = 0; cy < 2; cy++)
+        for (int cx = 0; cx < 2; cx++) {
+            const int x = xs[cx], y = ys[cy];
+            const int sx = x < 0 ? 1 : -1;
+            const int c = ext_idx(a, x, y), r1 = ext_idx(a, x + sx, y), r2 = ext_idx(a, x + 2 * sx, y);
+            T dp, dq;
+            dghost(E[r1], E[r2], dp, dq);
+            const T l = LE[c];
+            LE[r1] += l * dp;
+            LE[r2] += l * dq;
+            LE[c] = T(0);
+        }
+}
+
+// Transpose of the side ghosts: interior node j gets its own extended
+// adjoint plus the share of each side ghost extrapolated from it;
+// out = b1 + h b2 + b3 + that (null bases count as zero).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_ghostT(const AdjArgs a, const T *src, const T *LE, const T *b1, const T *b2, T h,
+             const T *b3, T *out) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int nx = a.nx, ny = a.ny;
+    const int x = i % nx, y = i / nx;
+    T s = LE[ext_idx(a, x, y)];
+    T dp, dq;
+    if (x <= 1) {   // left ghost of row y: ghost(src(0, y), src(1, y))
+        dghost(src[y * nx], src[y * nx + 1], dp, dq);
+        s += LE[ext_idx(a, -1, y)] * (x == 0 ? dp : dq);
+    }
+    if (x >= nx - 2) {   // right ghost: ghost(src(nx-1, y), src(nx-2, y))
+        dghost(src[y * nx + nx - 1], src[y * nx + nx - 2], dp, dq);
+        s += LE[ext_idx(a, nx, y)] * (x == nx - 1 ? dp : dq);
+    }
+    if (y <= 1) {   // bottom ghost of column x
+        dghost(src[x], src[nx + x], dp, dq);
+        s += LE[ext_idx(a, x, -1)] * (y == 0 ? dp : dq);
+    }
+    if (y >= ny - 2) {   // top ghost
+        dghost(src[(ny - 1) * nx + x], src[(ny - 2) * nx + x], dp, dq);
+        s += LE[ext_idx(a, x, ny)] * (y == ny - 1 ? dp : dq);
+    }
+    if (b1) s += b1[i];
+    if (b2) s += h * b2[i];
+    if (b3) s += b3[i];
+    out[i] = s;
+}
+
+// Transpose of the ignition minimum: dL/dpsi^n where no ignition set the
+// minimum; else the ignition's shift gets dL/dpsi' d(psi_g)/d(shift).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_ignT(const AdjArgs a, const T *LP0, const int8_t *sel, const fire_ignition *ign, T *L1,
+           double *acc) {
+    __shared__ double sh[kAB];
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    int g = -1;
+    double cx = 0.0, cy = 0.0;
+    if (i < a.nx * a.ny) {
+        const T l = LP0[i];
+        const int k = sel[i];
+        if (k < 0) {
+            L1[i] = l;
+        } else {
+            L1[i] = T(0);
+            IgnGeo<T> geo;
+            if (l != T(0) && ign_setup<T>(ign[k], a.t, geo)) {
+                const int x = i % a.nx, y = i / a.nx;
+                const T px = T(((double)x + 0.5) * a.dx - geo.ax);
+                const T py = T(((double)y + 0.5) * a.dy - geo.ay);
+                T s = (px * geo.ex + py * geo.ey) * geo.invL2;
+                s = vmin(vmax(s, T(0)), T(1));
+                const T qx = px - s * geo.ex, qy = py - s * geo.ey;
+                const T d = M<T>::sqrt(qx * qx + qy * qy);
+                if (d > T(0)) {
+                    g = k;
+                    cx = (double)(-l * M<T>::div(qx, d));
+                    cy = (double)(-l * M<T>::div(qy, d));
+                }
+            }
+        }
+    }
+    shift_reduce(g, cx, cy, a.nign, acc, sh);
+}
+
+// Node times t^ on the extended mesh: t' where psi >= 0 and on the ghosts,
+// else t_i (as the step kernel forms them for the fuel fraction).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_that(const AdjArgs a, const T *psi, const T *tign, T tp, T *TH) {
+    const int ex = a.nx + 2, ey = a.ny + 2;
+    const int j = blockIdx.x * kAB + threadIdx.x;
+    if (j >= ex * ey) return;
+    const int x = j % ex - 1, y = j / ex - 1;
+    T r = tp;
+    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny) {
+        const int i = y * a.nx + x;
+        r = psi[i] >= T(0) ? tp : tign[i];
+    }
+    TH[j] = r;
+}
+
+// dL/dpsi and dL/dt^ at extended node j from dL/dF of the (up to nine)
+// interior cells whose fuel-fraction stencil holds it.
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_frac(const AdjArgs a, const T *E, const T *TH, const T *lamF, const uint8_t *cat,
+           const T *coef, T tp, T *LE, T *LTH) {
+    const int ex = a.nx + 2, ey = a.ny + 2;
+    const int j = blockIdx.x * kAB + threadIdx.x;
+    if (j >= ex * ey) return;
+    const int x = j % ex - 1, y = j / ex - 1;
+    T sp = T(0), sq = T(0);
+    for (int oy = -1; oy <= 1; oy++)
+        for (int ox = -1; ox <= 1; ox++) {
+            const int cx = x + ox, cy = y + oy;
+            if (cx < 0 || cx >= a.nx || cy < 0 || cy >= a.ny) continue;
+            const int ci = cy * a.nx + cx;
+            const T lf = lamF[ci];
+            if (lf == T(0)) continue;
+            T p[3][3], q[3][3];
+            T mn = M<T>::inf();
+            for (int b = 0; b < 3; b++)
+                for (int aa = 0; aa < 3; aa++) {
+                    const int e = ext_idx(a, cx + aa - 1, cy + b - 1);
+                    p[b][aa] = E[e];
+                    q[b][aa] = TH[e];
+                    mn = vmin(mn, p[b][aa]);
+                }
+            if (!(mn < T(0))) continue;   // F = 1 exactly there
+            const int cv = cat[ci] < a.ncat - 1 ? cat[ci] : a.ncat - 1;
+            const T rTf = T(1) / coef[cv * kNCoef + kTf];
+            T gp[3][3], gq[3][3];
+            cell_fraction_grad(p, q, tp, rTf, gp, gq);
+            const int b = -oy + 1, aa = -ox + 1;   // node j within the cell's stencil
+            sp += lf * gp[b][aa];
+            sq += lf * gq[b][aa];
+        }
+    LE[j] = sp;
+    LTH[j] = sq;
+}
+
+// dL/dt_i from dL/dt^ where t^ = t_i (psi < 0).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_lt_init(const AdjArgs a, const T *psi, const T *LTH, T *LT) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    LT[i] = psi[i] < T(0) ? LTH[ext_idx(a, x, y)] : T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kAB) k_mark(int n, int32_t *set_step, const T *tign, int cnt) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= cnt) return;
+    if (set_step[i] < 0 && !is_inf(tign[i])) set_step[i] = n;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_tign_at(const int32_t *set_step, const T *tign, int s0, T *out, int cnt) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= cnt) return;
+    const int s = set_step[i];
+    out[i] = (s >= 0 && s < s0) ? tign[i] : M<T>::inf();
+}
+
+template <typename T> __global__ void __launch_bounds__(kAB) k_set(T *p, T v, size_t cnt) {
+    for (size_t i = blockIdx.x * (size_t)kAB + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kAB)
+        p[i] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kAB) k_cast(const double *src, T *dst, int cnt) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i < cnt) dst[i] = T(src[i]);
+}
+
+// Per-block, per-category sums of gm (fixed order), then column sums.
+__global__ void __launch_bounds__(kAB)
+k_cat_partial(const double *gm, const uint8_t *cat, int cnt, int ncat, double *part) {
+    __shared__ double sh[kAB];
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    const double v = i < cnt ? gm[i] : 0.0;
+    const int c = i < cnt ? (cat[i] < ncat - 1 ? cat[i] : ncat - 1) : -1;
+    for (int k = 0; k < ncat; k++) {
+        const int any = __syncthreads_or(c == k);
+        if (!any) {
+            if (threadIdx.x == 0) part[(size_t)blockIdx.x * ncat + k] = 0.0;
+            continue;
+        }
+        const double s = block_sum(c == k ? v : 0.0, sh);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * ncat + k] = s;
+    }
+}
+
+__global__ void k_col_sum(const double *part, int rows, int cols, double *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cols) return;
+    double s = 0.0;
+    for (int r = 0; r < rows; r++) s += part[(size_t)r * cols + k];
+    out[k] = s;
+}
+
+// ---------------------------------------------------------------- host side
+
+int hip_fail(hipError_t e) { return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP; }
+
+struct AdjLayout {
+    size_t ckpt, stack, set_step, tig, frac, flux, status, p0, b, e1, e2, le, th, sel, tsel, l1,
+        lt, lp0, lb, d, gu, gv, gm, acc, part, small, total;
+};
+
+}  // namespace
+}  // namespace fire
+
+using namespace fire;
+
+struct fire_adj {
+    fire_ctx *c;
+    int nsteps, every, nseg;
+    char *arena;
+    AdjLayout L;
+    std::vector<double> tstep;   // model time before step n (n = 0..nsteps)
+    const void *u, *v;
+    double dt;
+    int forward_done;
+    int nblk, nblk_ext;
+};
+
+namespace {
+
+AdjLayout adj_layout(const fire_mesh *m, int ncat, int nsteps, int every) {
+    const size_t n = (size_t)m->nx * m->ny, ne = (size_t)(m->nx + 2) * (m->ny + 2);
+    const size_t es = esize(m);
+    const size_t natm = (size_t)((m->nx + m->sr_x - 1) / m->sr_x) * ((m->ny + m->sr_y - 1) / m->sr_y);
+    const int nseg = (nsteps + every - 1) / every;
+    const size_t nblk = (n + kAB - 1) / kAB;
+    AdjLayout L;
+    size_t o = 0;
+    auto take = [&](size_t &f, size_t bytes) {
+        f = o;
+        o = align_up(o + bytes);
+    };
+    take(L.ckpt, (size_t)nseg * n * es);
+    take(L.stack, (size_t)(every + 1) * n * es);
+    take(L.set_step, n * 4);
+    take(L.tig, n * es);
+    take(L.frac, n * es);
+    take(L.flux, 2 * natm * es);
+    take(L.status, 64);
+    take(L.p0, n * es);
+    take(L.b, n * es);
+    take(L.e1, ne * es);
+    take(L.e2, ne * es);
+    take(L.le, ne * es);
+    take(L.th, ne * es);
+    take(L.sel, n);
+    take(L.tsel, n);
+    take(L.l1, n * es);
+    take(L.lt, n * es);
+    take(L.lp0, n * es);
+    take(L.lb, n * es);
+    take(L.d, 5 * n * es);
+    take(L.gu, n * 8);
+    take(L.gv, n * 8);
+    take(L.gm, n * 8);
+    take(L.acc, nblk * kShift * 8);
+    take(L.part, nblk * (size_t)(ncat > kShift ? ncat : kShift) * 8);
+    take(L.small, (size_t)(256 + kShift) * 8);
+    L.total = o;
+    return L;
+}
+
+template <typename T> struct Run {
+    fire_adj *A;
+    fire_ctx *c;
+    AdjArgs a;
+    hipStream_t s;
+    size_t n, ne;
+    int gn, ge;
+
+    template <typename P> P *at(size_t off) { return reinterpret_cast<P *>(A->arena + off); }
+    T *arr(size_t off) { return at<T>(off); }
+    T *stack(int k) { return arr(A->L.stack) + (size_t)k * n; }
+    const T *coef() { return reinterpret_cast<const T *>(c->arena + c->off_coef); }
+    const fire_ignition *ign() {
+        return reinterpret_cast<const fire_ignition *>(c->arena + c->off_ign);
+    }
+    const T *cur_psi() { return reinterpret_cast<const T *>(c->arena + c->off_psi[c->cur]); }
+    const T *tign_final() { return reinterpret_cast<const T *>(c->arena + c->off_tign); }
+
+    explicit Run(fire_adj *A_) : A(A_), c(A_->c), s(A_->c->stream) {
+        const fire_mesh &m = c->mesh;
+        std::memset(&a, 0, sizeof(a));
+        a.nx = m.nx;
+        a.ny = m.ny;
+        a.ncat = c->ncat;
+        a.nign = c->nign;
+        a.visc_mode = c->prm.viscosity_mode;
+        a.dx = m.dx;
+        a.dy = m.dy;
+        a.rdx = 1.0 / m.dx;
+        a.rdy = 1.0 / m.dy;
+        a.eps = c->prm.viscosity;
+        a.cap = c->prm.ros_cap;
+        a.dt = A->dt;
+        n = (size_t)m.nx * m.ny;
+        ne = (size_t)(m.nx + 2) * (m.ny + 2);
+        gn = (int)((n + kAB - 1) / kAB);
+        ge = (int)((ne + kAB - 1) / kAB);
+    }
+
+    hipError_t zero_d(size_t off, size_t cnt) {
+        hipLaunchKernelGGL(k_set<double>, dim3(256), dim3(kAB), 0, s, at<double>(off), 0.0, cnt);
+        return hipGetLastError();
+    }
+
+    // dL/dpsi^N and dL/dt_i from dL/dF_end
+    hipError_t loss_init(const T *dF) {
+        const T *psiN = cur_psi();
+        const T tp = T(A->tstep[A->nsteps]);
+        hipLaunchKernelGGL(k_ext<T>, dim3(ge), dim3(kAB), 0, s, a, psiN, arr(A->L.e1));
+        hipLaunchKernelGGL(k_that<T>, dim3(ge), dim3(kAB), 0, s, a, psiN, tign_final(), tp,
+                           arr(A->L.th));
+        hipLaunchKernelGGL(k_adj_frac<T>, dim3(ge), dim3(kAB), 0, s, a, arr(A->L.e1),
+                           arr(A->L.th), dF, c->cat, coef(), tp, arr(A->L.le), arr(A->L.e2));
+        hipLaunchKernelGGL(k_adj_corners<T>, dim3(1), dim3(64), 0, s, a, arr(A->L.e1),
+                           arr(A->L.le));
+        hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, psiN, arr(A->L.le),
+                           (const T *)nullptr, (const T *)nullptr, T(0), (const T *)nullptr,
+                           arr(A->L.l1));
+        hipLaunchKernelGGL(k_lt_init<T>, dim3(gn), dim3(kAB), 0, s, a, psiN, arr(A->L.e2),
+                           arr(A->L.lt));
+        return hipGetLastError();
+    }
+
+    hipError_t replay(int seg) {
+        const int s0 = seg * A->every;
+        const int s1 = s0 + A->every < A->nsteps ? s0 + A->every : A->nsteps;
+        hipError_t h = hipMemcpyAsync(stack(0), arr(A->L.ckpt) + (size_t)seg * n, n * sizeof(T),
+                                      hipMemcpyDeviceToDevice, s);
+        if (h != hipSuccess) return h;
+        hipLaunchKernelGGL(k_tign_at<T>, dim3(gn), dim3(kAB), 0, s, at<int32_t>(A->L.set_step),
+                           tign_final(), s0, arr(A->L.tig), (int)n);
+        hipLaunchKernelGGL(k_set<T>, dim3(256), dim3(kAB), 0, s, arr(A->L.frac), T(1), n);
+        const size_t natm = (size_t)((c->mesh.nx + c->mesh.sr_x - 1) / c->mesh.sr_x) *
+                            ((c->mesh.ny + c->mesh.sr_y - 1) / c->mesh.sr_y);
+        for (int k = s0; k < s1; k++) {
+            h = step_raw(c, stack(k - s0), stack(k - s0 + 1), arr(A->L.tig), arr(A->L.frac), A->u,
+                         A->v, A->tstep[k], A->dt, arr(A->L.flux), arr(A->L.flux) + natm,
+                         at<int>(A->L.status));
+            if (h != hipSuccess) return h;
+        }
+        return hipGetLastError();
+    }
+
+    hipError_t reverse_step(int n_, int k) {
+        a.t = A->tstep[n_];
+        const T *psi_n = stack(k), *psi_n1 = stack(k + 1);
+        const T *u = (const T *)A->u, *v = (const T *)A->v;
+        const T *gx = (const T *)c->dzdx, *gy = (const T *)c->dzdy;
+        T *P0 = arr(A->L.p0), *B = arr(A->L.b), *E1 = arr(A->L.e1), *E2 = arr(A->L.e2);
+        T *LE = arr(A->L.le), *L1 = arr(A->L.l1), *LT = arr(A->L.lt), *LP0 = arr(A->L.lp0);
+        T *LB = arr(A->L.lb), *D = arr(A->L.d);
+        double *gu = at<double>(A->L.gu), *gv = at<double>(A->L.gv), *gm = at<double>(A->L.gm);
+        double *acc = at<double>(A->L.acc);
+        int8_t *sel = at<int8_t>(A->L.sel), *tsel = at<int8_t>(A->L.tsel);
+        const T dt = T(A->dt);
+        // recompute the step's intermediate states
+        hipLaunchKernelGGL(k_adj_ignite<T>, dim3(gn), dim3(kAB), 0, s, a, ign(), psi_n, P0, sel,
+                           tsel);
+        hipLaunchKernelGGL(k_ext<T>, dim3(ge), dim3(kAB), 0, s, a, P0, E1);
+        hipLaunchKernelGGL(k_adj_stage<T>, dim3(gn), dim3(kAB), 0, s, a, E1, P0, u, v, gx, gy,
+                           c->cat, coef(), B);
+        hipLaunchKernelGGL(k_ext<T>, dim3(ge), dim3(kAB), 0, s, a, B, E2);
+        // ignition times set in this step
+        hipLaunchKernelGGL(k_adj_cross<T>, dim3(gn), dim3(kAB), 0, s, a, n_,
+                           at<int32_t>(A->L.set_step), P0, psi_n1, L1, LT, LP0, tsel, ign(), acc);
+        // stage 2: psi^{n+1} = (psi' + psi*)/2 + dt/2 F(G psi*)
+        hipLaunchKernelGGL(k_adj_rhs<T>, dim3(gn), dim3(kAB), 0, s, a, E2, L1, T(0.5) * dt, u, v,
+                           gx, gy, c->cat, coef(), D, gu, gv, gm);
+        hipLaunchKernelGGL(k_adj_gather<T>, dim3(ge), dim3(kAB), 0, s, a, D, LE);
+        hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, B, LE,
+                           (const T *)nullptr, L1, T(0.5), (const T *)nullptr, LB);
+        // stage 1: psi* = psi' + dt F(G psi')
+        hipLaunchKernelGGL(k_adj_rhs<T>, dim3(gn), dim3(kAB), 0, s, a, E1, LB, dt, u, v, gx, gy,
+                           c->cat, coef(), D, gu, gv, gm);
+        hipLaunchKernelGGL(k_adj_gather<T>, dim3(ge), dim3(kAB), 0, s, a, D, LE);
+        hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, P0, LE, LP0, L1,
+                           T(0.5), LB, LP0);
+        // ignition minimum
+        hipLaunchKernelGGL(k_adj_ignT<T>, dim3(gn), dim3(kAB), 0, s, a, LP0, sel, ign(), L1, acc);
+        return hipGetLastError();
+    }
+
+    int backward(const T *dF, T *grad_u, T *grad_v, double *grad_mult, double *grad_shift) {
+        hipError_t h = zero_d(A->L.gu, n);
+        if (h == hipSuccess) h = zero_d(A->L.gv, n);
+        if (h == hipSuccess) h = zero_d(A->L.gm, n);
+        if (h == hipSuccess) h = zero_d(A->L.acc, (size_t)gn * kShift);
+        if (h == hipSuccess) h = loss_init(dF);
+        for (int seg = A->nseg - 1; seg >= 0 && h == hipSuccess; seg--) {
+            const int s0 = seg * A->every;
+            const int s1 = s0 + A->every < A->nsteps ? s0 + A->every : A->nsteps;
+            h = replay(seg);
+            for (int k = s1 - 1; k >= s0 && h == hipSuccess; k--) h = reverse_step(k, k - s0);
+        }
+        if (h != hipSuccess) return FIRE_ERR_HIP;
+        // outputs
+        hipLaunchKernelGGL(k_cast<T>, dim3(gn), dim3(kAB), 0, s, at<double>(A->L.gu), grad_u,
+                           (int)n);
+        hipLaunchKernelGGL(k_cast<T>, dim3(gn), dim3(kAB), 0, s, at<double>(A->L.gv), grad_v,
+                           (int)n);
+        double *part = at<double>(A->L.part), *small = at<double>(A->L.small);
+        hipLaunchKernelGGL(k_cat_partial, dim3(gn), dim3(kAB), 0, s, at<double>(A->L.gm), c->cat,
+                           (int)n, c->ncat, part);
+        hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, s, part, gn, c->ncat, small);
+        hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, at<double>(A->L.acc), gn, kShift,
+                           small + 256);
+        h = hipGetLastError();
+        if (h == hipSuccess)
+            h = hipMemcpyAsync(grad_mult, small, sizeof(double) * c->ncat, hipMemcpyDeviceToHost,
+                               s);
+        std::vector<double> sh(kShift);
+        if (h == hipSuccess)
+            h = hipMemcpyAsync(sh.data(), small + 256, sizeof(double) * kShift,
+                               hipMemcpyDeviceToHost, s);
+        if (h == hipSuccess) h = hipStreamSynchronize(s);
+        if (h != hipSuccess) return FIRE_ERR_HIP;
+        if (grad_shift)
+            for (int g = 0; g < c->nign; g++) {
+                grad_shift[2 * g] = sh[2 * g];
+                grad_shift[2 * g + 1] = sh[2 * g + 1];
+            }
+        return FIRE_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t fire_adj_bytes(const fire_mesh *mesh, int32_t ncat, int32_t nsteps, int32_t every) {
+    if (!mesh_ok(mesh) || ncat < 1 || ncat > 256 || nsteps < 1 || every < 1) return 0;
+    if ((size_t)(mesh->nx + 2) * (mesh->ny + 2) > ((size_t)1 << 31)) return 0;
+    return adj_layout(mesh, ncat, nsteps, every).total;
+}
+
+int fire_adj_init(fire_adj **out, fire_ctx *c, int32_t nsteps, int32_t every, void *scratch,
+                  size_t scratch_bytes) {
+    if (!out) return FIRE_ERR_ARG;
+    *out = nullptr;
+    if (!c || nsteps < 1 || every < 1 || !scratch || ((uintptr_t)scratch % kAlign) != 0)
+        return FIRE_ERR_ARG;
+    if (scratch_bytes < fire_adj_bytes(&c->mesh, c->ncat, nsteps, every)) return FIRE_ERR_ARG;
+    fire_adj *A = new (std::nothrow) fire_adj();
+    if (!A) return FIRE_ERR_OOM;
+    A->c = c;
+    A->nsteps = nsteps;
+    A->every = every;
+    A->nseg = (nsteps + every - 1) / every;
+    A->arena = (char *)scratch;
+    A->L = adj_layout(&c->mesh, c->ncat, nsteps, every);
+    A->u = A->v = nullptr;
+    A->dt = 0.0;
+    A->forward_done = 0;
+    *out = A;
+    return FIRE_OK;
+}
+
+int fire_adj_forward(fire_adj *A, const void *u, const void *v, double dt) {
+    if (!A || !u || !v || !(dt > 0.0) || !std::isfinite(dt)) return FIRE_ERR_ARG;
+    fire_ctx *c = A->c;
+    const size_t n = (size_t)c->mesh.nx * c->mesh.ny;
+    const size_t es = esize(&c->mesh);
+    const int gn = (int)((n + kAB - 1) / kAB);
+    const size_t natm = (size_t)((c->mesh.nx + c->mesh.sr_x - 1) / c->mesh.sr_x) *
+                        ((c->mesh.ny + c->mesh.sr_y - 1) / c->mesh.sr_y);
+    A->u = u;
+    A->v = v;
+    A->dt = dt;
+    A->forward_done = 0;
+    A->tstep.assign(A->nsteps + 1, 0.0);
+    A->tstep[0] = c->t;
+    int32_t *set_step = reinterpret_cast<int32_t *>(A->arena + A->L.set_step);
+    hipLaunchKernelGGL(k_set<int32_t>, dim3(256), dim3(kAB), 0, c->stream, set_step, -1, n);
+    if (hipGetLastError() != hipSuccess) return FIRE_ERR_HIP;
+    char *flux = A->arena + A->L.flux;
+    for (int k = 0; k < A->nsteps; k++) {
+        if (k % A->every == 0) {
+            const hipError_t h =
+                hipMemcpyAsync(A->arena + A->L.ckpt + (size_t)(k / A->every) * n * es,
+                               c->arena + c->off_psi[c->cur], n * es, hipMemcpyDeviceToDevice,
+                               c->stream);
+            if (h != hipSuccess) return FIRE_ERR_HIP;
+        }
+        const int rc = fire_step(c, u, v, dt, flux, flux + natm * es, nullptr);
+        if (rc != FIRE_OK) return rc;
+        if (c->mesh.dtype == FIRE_F64)
+            hipLaunchKernelGGL(k_mark<double>, dim3(gn), dim3(kAB), 0, c->stream, k, set_step,
+                               (const double *)(c->arena + c->off_tign), (int)n);
+        else
+            hipLaunchKernelGGL(k_mark<float>, dim3(gn), dim3(kAB), 0, c->stream, k, set_step,
+                               (const float *)(c->arena + c->off_tign), (int)n);
+        if (hipGetLastError() != hipSuccess) return FIRE_ERR_HIP;
+        A->tstep[k + 1] = c->t;
+    }
+    A->forward_done = 1;
+    return FIRE_OK;
+}
+
+int fire_adj_backward(fire_adj *A, const void *dF, void *grad_u, void *grad_v, double *grad_mult,
+                      double *grad_shift) {
+    if (!A || !dF || !grad_u || !grad_v || !grad_mult) return FIRE_ERR_ARG;
+    if (!A->forward_done || A->c->t != A->tstep[A->nsteps]) return FIRE_ERR_STATE;
+    if (A->c->mesh.dtype == FIRE_F64) {
+        Run<double> r(A);
+        return r.backward((const double *)dF, (double *)grad_u, (double *)grad_v, grad_mult,
+                          grad_shift);
+    }
+    Run<float> r(A);
+    return r.backward((const float *)dF, (float *)grad_u, (float *)grad_v, grad_mult, grad_shift);
+}
+
+void fire_adj_destroy(fire_adj *A) { delete A; }
+
+}  // extern "C"

@@ -10,23 +10,6 @@
 
 using namespace fire;
 
-struct fire_ctx {
-    fire_mesh mesh;
-    fire_params prm;
-    int ncat;
-    int nign;
-    fire_ignition ign[FIRE_MAX_IGNITIONS];
-    const uint8_t *cat;
-    const void *dzdx, *dzdy;
-    char *arena;
-    size_t off_coef, off_fuel, off_ign, off_status, off_psi[2], off_tign, off_frac;
-    int cur;               // index of the current psi buffer
-    double t;              // model time of the current state
-    hipStream_t stream;
-    int tile_x, tile_y;
-    int stopped;           // boundary reached under the stop policy
-};
-
 namespace fire {
 
 bool mesh_ok(const fire_mesh *m) {
@@ -130,6 +113,65 @@ void *state_ptr(fire_ctx *c, size_t off) { return c->arena + off; }
 
 }  // namespace
 
+namespace fire {
+// One step of the context's mesh on explicit buffers (the context's own
+// arena for fire_step, replay buffers for the adjoint).
+hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
+                    const void *u, const void *v, double t, double dt, void *flux_sens,
+                    void *flux_lat, int *status) {
+    const fire_mesh &m = c->mesh;
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = m.nx;
+    a.ny = m.ny;
+    a.tile_x = c->tile_x;
+    a.tile_y = c->tile_y;
+    a.tiles_x = (m.nx + c->tile_x - 1) / c->tile_x;
+    const int tiles_y = (m.ny + c->tile_y - 1) / c->tile_y;
+    a.ntiles = a.tiles_x * tiles_y;
+    a.per_xcd = (a.ntiles + 7) / 8;
+    a.sr_x = m.sr_x;
+    a.sr_y = m.sr_y;
+    a.nax = (m.nx + m.sr_x - 1) / m.sr_x;
+    a.nay = (m.ny + m.sr_y - 1) / m.sr_y;
+    a.ncat = c->ncat;
+    a.guard = c->prm.guard_width;
+    a.visc_mode = c->prm.viscosity_mode;
+    a.nign = c->nign;
+    a.dx = m.dx;
+    a.dy = m.dy;
+    a.rdx = 1.0 / m.dx;
+    a.rdy = 1.0 / m.dy;
+    a.t = t;
+    a.dt = dt;
+    a.eps = c->prm.viscosity;
+    a.ros_cap = c->prm.ros_cap;
+
+    StepBuffers b;
+    b.psi_in = psi_in;
+    b.psi_out = psi_out;
+    b.tign = tign;
+    b.frac = frac;
+    b.u = u;
+    b.v = v;
+    b.dzdx = c->dzdx;
+    b.dzdy = c->dzdy;
+    b.cat = c->cat;
+    b.coef = state_ptr(c, c->off_coef);
+    b.fsens = flux_sens;
+    b.flat = flux_lat;
+    b.status = status;
+    b.ign = (const fire_ignition *)state_ptr(c, c->off_ign);
+    b.ncells = (size_t)m.nx * m.ny;
+    b.ens_doms = nullptr;
+    b.ens_tile_dom = nullptr;
+    b.ens_clock = nullptr;
+
+    return launch_step(m.dtype, a, b, c->stream);
+}
+
+}  // namespace fire
+
 extern "C" {
 
 int fire_abi_version(void) { return FIRE_ABI_VERSION; }
@@ -224,61 +266,17 @@ int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_s
     if (c->stopped) return FIRE_ERR_BOUNDARY;
     const fire_mesh &m = c->mesh;
 
-    StepArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.nx = m.nx;
-    a.ny = m.ny;
-    a.tile_x = c->tile_x;
-    a.tile_y = c->tile_y;
-    a.tiles_x = (m.nx + c->tile_x - 1) / c->tile_x;
-    const int tiles_y = (m.ny + c->tile_y - 1) / c->tile_y;
-    a.ntiles = a.tiles_x * tiles_y;
-    a.per_xcd = (a.ntiles + 7) / 8;
-    a.sr_x = m.sr_x;
-    a.sr_y = m.sr_y;
-    a.nax = (m.nx + m.sr_x - 1) / m.sr_x;
-    a.nay = (m.ny + m.sr_y - 1) / m.sr_y;
-    a.ncat = c->ncat;
-    a.guard = c->prm.guard_width;
-    a.visc_mode = c->prm.viscosity_mode;
-    a.nign = c->nign;
-    a.dx = m.dx;
-    a.dy = m.dy;
-    a.rdx = 1.0 / m.dx;
-    a.rdy = 1.0 / m.dy;
-    a.t = c->t;
-    a.dt = dt;
-    a.eps = c->prm.viscosity;
-    a.ros_cap = c->prm.ros_cap;
-
-    StepBuffers b;
-    b.psi_in = state_ptr(c, c->off_psi[c->cur]);
-    b.psi_out = state_ptr(c, c->off_psi[1 - c->cur]);
-    b.tign = state_ptr(c, c->off_tign);
-    b.frac = state_ptr(c, c->off_frac);
-    b.u = u;
-    b.v = v;
-    b.dzdx = c->dzdx;
-    b.dzdy = c->dzdy;
-    b.cat = c->cat;
-    b.coef = state_ptr(c, c->off_coef);
-    b.fsens = flux_sens;
-    b.flat = flux_lat;
-    b.status = (int *)state_ptr(c, c->off_status);
-    b.ign = (const fire_ignition *)state_ptr(c, c->off_ign);
-    b.ncells = (size_t)m.nx * m.ny;
-    b.ens_doms = nullptr;
-    b.ens_tile_dom = nullptr;
-    b.ens_clock = nullptr;
-
-    hipError_t e = launch_step(m.dtype, a, b, c->stream);
+    hipError_t e = step_raw(c, state_ptr(c, c->off_psi[c->cur]),
+                            state_ptr(c, c->off_psi[1 - c->cur]), state_ptr(c, c->off_tign),
+                            state_ptr(c, c->off_frac), u, v, c->t, dt, flux_sens, flux_lat,
+                            (int *)state_ptr(c, c->off_status));
     if (e != hipSuccess) return FIRE_ERR_HIP;
     c->cur = 1 - c->cur;
     c->t += dt;
     if (out) {
         out->psi = state_ptr(c, c->off_psi[c->cur]);
-        out->tign = b.tign;
-        out->frac = b.frac;
+        out->tign = state_ptr(c, c->off_tign);
+        out->frac = state_ptr(c, c->off_frac);
         out->t = c->t;
     }
     if (c->prm.boundary_policy == 0) {

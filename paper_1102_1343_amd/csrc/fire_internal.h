@@ -80,6 +80,30 @@ struct StepBuffers {
     const EnsClock *ens_clock;          // the clock says which is current
 };
 
+}  // namespace fire
+
+// A single-domain context (host side).  The arena holds, at these offsets,
+// the coefficient table, the fuel staging copy, the ignition records, the
+// status word, psi (two buffers), t_i and F.
+struct fire_ctx {
+    fire_mesh mesh;
+    fire_params prm;
+    int ncat;
+    int nign;
+    fire_ignition ign[FIRE_MAX_IGNITIONS];
+    const uint8_t *cat;
+    const void *dzdx, *dzdy;
+    char *arena;
+    size_t off_coef, off_fuel, off_ign, off_status, off_psi[2], off_tign, off_frac;
+    int cur;               // index of the current psi buffer
+    double t;              // model time of the current state
+    hipStream_t stream;
+    int tile_x, tile_y;
+    int stopped;           // boundary reached under the stop policy
+};
+
+namespace fire {
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_step(int dtype, const StepArgs &a, const StepBuffers &b, hipStream_t s);
 hipError_t launch_coef(int dtype, const fire_fuel *fuels_dev, int ncat, double wind_cap,
@@ -102,5 +126,8 @@ bool fuels_ok(const fire_fuel *cats, int ncat);
 bool ignitions_ok(const fire_ignition *ign, int nign);
 void default_tile(const fire_mesh *m, int *tx, int *ty);
 bool tile_ok(const fire_mesh *m, int tile_x, int tile_y);
+hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
+                    const void *u, const void *v, double t, double dt, void *flux_sens,
+                    void *flux_lat, int *status);
 
 }  // namespace fire

@@ -15,168 +15,19 @@
 // dz/dy, category and one write of psi and F (t_i only where it changes);
 // halo re-reads come from L2.  Work-groups are remapped so that each of the
 // eight XCDs sweeps a contiguous band of tiles, keeping halo rows in its L2.
-#include "fire_internal.h"
-
-#include <cmath>
+#include "fire_device.h"
 
 namespace fire {
 namespace {
 
-// ---------------------------------------------------------------- math
-template <typename T> struct M;
-
-template <> struct M<float> {
-    // x >= 0; x = 0 gives 0 for b > 0
-    static __device__ __forceinline__ float powp(float x, float b) {
-        return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(x));
-    }
-    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-    static __device__ __forceinline__ float div(float a, float b) {
-        return a * __builtin_amdgcn_rcpf(b);
-    }
-    // 1 - exp(-x); its absolute rounding error is that of F itself
-    static __device__ __forceinline__ float one_m_exp_neg(float x) {
-        return 1.0f - __builtin_amdgcn_exp2f(-1.4426950408889634f * x);
-    }
-    static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
-};
-
-template <> struct M<double> {
-    static __device__ __forceinline__ double powp(double x, double b) { return ::pow(x, b); }
-    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
-    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-    static __device__ __forceinline__ double one_m_exp_neg(double x) { return -::expm1(-x); }
-    static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
-};
-
-// max / min / |.| as single instructions (for non-NaN operands the same as
-// the comparisons they replace; a NaN operand yields the other one)
-__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
-__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
-__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
-__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
-__device__ __forceinline__ float vabs(float a) { return __builtin_fabsf(a); }
-__device__ __forceinline__ double vabs(double a) { return __builtin_fabs(a); }
-template <typename T> __device__ __forceinline__ bool is_inf(T a) { return a == M<T>::inf(); }
-
-// Spread rate, Eq. (3), with the category multiplier and the cap:
-// S = min{cap, m max{S0, R0 + c min{e, max{0,U}}^b + d max{0, tan phi}^2}}.
-template <typename T>
-__device__ __forceinline__ T ros(const T *row, T un, T tn, T cap) {
-    const T U = vmin(vmax(un, T(0)), row[kE]);
-    const T g = vmax(tn, T(0));
-    T s = row[kR0] + row[kC] * M<T>::powp(U, row[kB]) + row[kD] * g * g;
-    s = vmax(s, row[kS0]);
-    return vmin(row[kM] * s, cap);
-}
-
-// Boundary extrapolation of Sect. 4.1: never below either source node.
-template <typename T> __device__ __forceinline__ T ghost(T pb, T pb1) {
-    return vmax(pb + (pb - pb1), vmax(pb, pb1));
-}
-
-template <typename T> struct Consts {
-    T rdx, rdy, eps, cap;
-    int visc_mode;
-};
-
-// Per-category row of the in-LDS table, the multiplier m_k folded in
-// (m max{S0, R0 + c U^b + d g^2} = max{m S0, m R0 + m c U^b + m d g^2}, m >= 0).
-enum { kLR0, kLC, kLD, kLB, kLE, kLS0, kLTf, kLCh, kLCq, kLPad0, kLPad1, kLPad2, kLRow };
-
-template <typename T> struct alignas(4 * sizeof(T)) V4 { T x, y, z, w; };
-
-// Spread rate, Eq. (3), with multiplier and cap, from an LDS table row.
-template <typename T>
-__device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
-    const V4<T> r0 = *reinterpret_cast<const V4<T> *>(row);       // R0 c d b
-    const V4<T> r1 = *reinterpret_cast<const V4<T> *>(row + 4);   // e S0 Tf Ch
-    const T U = vmin(vmax(un, T(0)), r1.x);
-    const T g = vmax(tn, T(0));
-    const T s = r0.x + r0.y * M<T>::powp(U, r0.w) + r0.z * (g * g);
-    return vmin(vmax(s, r1.y), cap);
-}
+using namespace dev;
 
 // Right-hand side of Eq. (12) at frame cell (fy, fx) of the level set P.
-// The Godunov choice of Eq. (13) enters only through its square, which for
-// every sign pattern is max(max(D-,0)^2, min(D+,0)^2); the dx-scaled
-// Laplacian is (D+ - D-) summed over x and y.  The central gradient is taken
-// as (psi_E - psi_W)/dx (its factor 1/2 cancels in the normal) straight from
-// the two nodes, so it is exactly zero when they are equal -- as at a domain
-// corner whose ghosts mirror the inner nodes -- whatever the compiler fuses.
 template <typename T>
 __device__ __forceinline__ T rhs(const T (*P)[kFW], int fy, int fx, T u, T v, T gzx, T gzy,
                                  const T *row, const Consts<T> &c) {
-    const T pc = P[fy][fx], pw = P[fy][fx - 1], pe = P[fy][fx + 1];
-    const T ps = P[fy - 1][fx], pn = P[fy + 1][fx];
-    const T dmx = (pc - pw) * c.rdx, dpx = (pe - pc) * c.rdx;
-    const T dmy = (pc - ps) * c.rdy, dpy = (pn - pc) * c.rdy;
-    const T ax = vmax(dmx, T(0)), bx = vmin(dpx, T(0));
-    const T ay = vmax(dmy, T(0)), by = vmin(dpy, T(0));
-    const T gx2 = vmax(ax * ax, bx * bx), gy2 = vmax(ay * ay, by * by);
-    const T up = M<T>::sqrt(gx2 + gy2);
-    const T cx = (pe - pw) * c.rdx, cy = (pn - ps) * c.rdy;
-    const T cn2 = cx * cx + cy * cy;
-    const T inv = cn2 > T(0) ? M<T>::rsqrt(cn2) : T(0);
-    const T nx = cx * inv, ny = cy * inv;
-    const T S = ros_row(row, u * nx + v * ny, gzx * nx + gzy * ny, c.cap);
-    const T lap = (dpx - dmx) + (dpy - dmy);
-    const T visc = c.visc_mode == 0 ? c.eps * S * lap : c.eps * lap;
-    return visc - S * up;
-}
-
-// One ignition's geometry at time t.  The segment start stays in double so
-// node offsets are formed exactly from global coordinates: psi_g at a node
-// is then the same in every tile that touches the node (owner or halo).
-template <typename T> struct IgnGeo {
-    double ax, ay;
-    T ex, ey, invL2, rad, tg, lenv, invS, t;
-};
-
-template <typename T>
-__device__ __forceinline__ bool ign_setup(const fire_ignition &g, double t, IgnGeo<T> &o) {
-    const bool torch = (g.vx != 0.0 || g.vy != 0.0);
-    const double tend = torch ? g.t_end : g.t_start;
-    const bool inst = __builtin_isinf(g.ros);
-    const double grow = inst ? 0.0 : g.radius / g.ros;
-    if (!(t >= g.t_start && t <= tend + grow)) return false;
-    double bx = g.bx, by = g.by;
-    if (torch) {
-        const double te = t < g.t_end ? t : g.t_end;
-        bx = g.ax + g.vx * (te - g.t_start);
-        by = g.ay + g.vy * (te - g.t_start);
-    }
-    const double ex = bx - g.ax, ey = by - g.ay;
-    const double L2 = ex * ex + ey * ey;
-    const double r = g.ros * (t - g.t_start);
-    o.ax = g.ax;
-    o.ay = g.ay;
-    o.ex = T(ex);
-    o.ey = T(ey);
-    o.invL2 = L2 > 0.0 ? T(1.0 / L2) : T(0);
-    o.rad = T(inst ? g.radius : (r < g.radius ? r : g.radius));
-    o.tg = T(g.t_start);
-    o.lenv = torch ? T(::sqrt(L2) / ::sqrt(g.vx * g.vx + g.vy * g.vy)) : T(0);
-    o.invS = inst ? T(0) : T(1.0 / g.ros);
-    o.t = T(t);
-    return true;
-}
-
-// psi_g of Eq. (20) (drip-torch form) at the node whose centre is
-// (px, py) away from the segment start (differences formed in double from
-// global coordinates), and the arrival time of the initial fire there,
-// capped at t.
-template <typename T>
-__device__ __forceinline__ T ign_psi(const IgnGeo<T> &g, T px, T py, T &arrive) {
-    T s = (px * g.ex + py * g.ey) * g.invL2;
-    s = vmin(vmax(s, T(0)), T(1));
-    const T qx = px - s * g.ex, qy = py - s * g.ey;
-    const T d = M<T>::sqrt(qx * qx + qy * qy);
-    const T a = g.tg + s * g.lenv + d * g.invS;
-    arrive = vmin(a, g.t);
-    return d - g.rad;
+    return rhs5(P[fy][fx], P[fy][fx - 1], P[fy][fx + 1], P[fy - 1][fx], P[fy + 1][fx], u, v, gzx,
+                gzy, row, c);
 }
 
 // Global loads/stores at element index i.  With SMALL (every array below
@@ -301,21 +152,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     const uint32_t off0 = cbase + (uint32_t)((y0 - kHalo) * nx + gx);
     const uint32_t unx = (uint32_t)nx;
 
-    for (int i = tid; i < a.ncat; i += kBlock) {
-        const T *g = coef + i * kNCoef;
-        T *r = tab + i * kLRow;
-        const T m = g[kM];
-        r[kLR0] = m * g[kR0];
-        r[kLC] = m * g[kC];
-        r[kLD] = m * g[kD];
-        r[kLB] = g[kB];
-        r[kLE] = g[kE];
-        r[kLS0] = m * g[kS0];
-        r[kLTf] = T(1) / g[kTf];
-        r[kLCh] = g[kCh];
-        r[kLCq] = g[kCq];
-        r[kLPad0] = r[kLPad1] = r[kLPad2] = T(0);
-    }
+    for (int i = tid; i < a.ncat; i += kBlock) make_row(coef + i * kNCoef, tab + i * kLRow);
 
     Consts<T> c;
     c.rdx = T(a.rdx);

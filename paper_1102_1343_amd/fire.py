@@ -108,6 +108,13 @@ def lib():
         L.fire_ens_set_stream.argtypes = [vp, vp]
         L.fire_ens_destroy.argtypes = [vp]
         L.fire_ens_destroy.restype = None
+        L.fire_adj_bytes.argtypes = [P(fire_mesh), C.c_int32, C.c_int32, C.c_int32]
+        L.fire_adj_bytes.restype = C.c_size_t
+        L.fire_adj_init.argtypes = [P(vp), vp, C.c_int32, C.c_int32, vp, C.c_size_t]
+        L.fire_adj_forward.argtypes = [vp, vp, vp, C.c_double]
+        L.fire_adj_backward.argtypes = [vp, vp, vp, vp, P(C.c_double), P(C.c_double)]
+        L.fire_adj_destroy.argtypes = [vp]
+        L.fire_adj_destroy.restype = None
         _lib = L
     return _lib
 
@@ -169,6 +176,7 @@ class Fire:
         self.mesh = fire_mesh(self.nx, self.ny, float(dx), float(dy), int(sr_x), int(sr_y),
                               FIRE_F64 if dtype == torch.float64 else FIRE_F32, 0)
         self.ncat = len(fuels)
+        self.nign = len(ignitions)
         self.cat = self._dev(cat, torch.uint8)
         if int(self.cat.max()) >= self.ncat:
             raise ValueError("fuel category map holds a value >= number of fuels")
@@ -495,3 +503,102 @@ class FireEnsemble:
             self.close()
         except Exception:
             pass
+
+
+class FireAdjoint:
+    """Differentiable run of a ``Fire`` context: ``forward`` steps it
+    ``nsteps`` times under one wind, keeping psi every ``every`` steps;
+    ``backward(dF)`` returns dL/du, dL/dv (device tensors), dL/dm_k (numpy,
+    per category) and dL/d(shift) (numpy [nign, 2]) for dF = dL/dF_end."""
+
+    def __init__(self, fire, nsteps, every=50):
+        self.fire = fire
+        self.nsteps, self.every = int(nsteps), int(every)
+        nb = lib().fire_adj_bytes(C.byref(fire.mesh), fire.ncat, self.nsteps, self.every)
+        if nb == 0:
+            raise FireError(-1, "fire_adj_bytes")
+        self.scratch = torch.empty(nb + 256, dtype=torch.uint8, device=fire.device)
+        base = self.scratch.data_ptr() + (-self.scratch.data_ptr()) % 256
+        h = C.c_void_p()
+        _check(lib().fire_adj_init(C.byref(h), fire._ctx, self.nsteps, self.every,
+                                   C.c_void_p(base), nb), "fire_adj_init")
+        self._h = h
+        self._wind = None
+
+    def forward(self, u, v, dt):
+        f = self.fire
+        for t in (u, v):
+            if t.dtype != f.dtype or not t.is_contiguous() or t.shape != (f.ny, f.nx):
+                raise ValueError("wind must be contiguous [ny, nx] tensors of the fire dtype")
+        self._wind = (u, v)     # the library keeps the pointers until backward
+        _check(lib().fire_adj_forward(self._h, C.c_void_p(u.data_ptr()),
+                                      C.c_void_p(v.data_ptr()), float(dt)), "fire_adj_forward")
+        return f.frac
+
+    def backward(self, dF):
+        f = self.fire
+        if dF.dtype != f.dtype or not dF.is_contiguous() or dF.shape != (f.ny, f.nx):
+            raise ValueError("dF must be a contiguous [ny, nx] tensor of the fire dtype")
+        gu = torch.empty_like(dF)
+        gv = torch.empty_like(dF)
+        gm = np.zeros(f.ncat)
+        gs = np.zeros((max(1, f.nign), 2))
+        _check(lib().fire_adj_backward(self._h, C.c_void_p(dF.data_ptr()),
+                                       C.c_void_p(gu.data_ptr()), C.c_void_p(gv.data_ptr()),
+                                       gm.ctypes.data_as(C.POINTER(C.c_double)),
+                                       gs.ctypes.data_as(C.POINTER(C.c_double))),
+               "fire_adj_backward")
+        return gu, gv, gm, gs[:f.nign]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fire_adj_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def shifted_ignitions(ignitions, shift):
+    """Ignitions translated by shift[g] = (dx, dy) metres (start and end)."""
+    out = []
+    for g, (sx, sy) in zip(ignitions, shift):
+        out.append(dict(g, ax=g["ax"] + sx, ay=g["ay"] + sy, bx=g["bx"] + sx, by=g["by"] + sy))
+    return out
+
+
+class FireRun(torch.autograd.Function):
+    """F_end = run(u, v, m, shift): ``nsteps`` fire steps of ``prob`` (a
+    ``synth.Problem``) under the wind (u, v), with per-category spread
+    multipliers m and ignitions translated by shift [nign, 2]; differentiable
+    in all four through the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, u, v, mult, shift, prob, nsteps, every=50, dtype=torch.float64):
+        fuels = [dict(f, ros_mult=float(m)) for f, m in zip(prob.fuels, mult.tolist())]
+        igns = shifted_ignitions(prob.ignitions, shift.detach().cpu().tolist())
+        p = dict(prob.params)
+        fire = Fire(prob.nx, prob.ny, prob.dx, prob.dy, prob.sr_x, prob.sr_y, fuels, prob.cat,
+                    prob.dzdx, prob.dzdy, igns, dtype=dtype, device=u.device,
+                    **{k: v_ for k, v_ in p.items() if k in (
+                        "viscosity", "psi_init", "wind_cap", "ros_cap", "t0", "guard_width",
+                        "boundary_policy", "viscosity_mode")})
+        adj = FireAdjoint(fire, nsteps, every)
+        uu = u.detach().to(dtype).contiguous()
+        vv = v.detach().to(dtype).contiguous()
+        F = adj.forward(uu, vv, prob.dt).clone()
+        ctx.adj = adj
+        ctx.keep = (fire, uu, vv)
+        ctx.meta = (u.dtype, v.dtype, mult.dtype, mult.device, shift.dtype, shift.device)
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        udt, vdt, mdt, mdev, sdt, sdev = ctx.meta
+        fire = ctx.keep[0]
+        gu, gv, gm, gs = ctx.adj.backward(gF.detach().to(fire.dtype).contiguous())
+        return (gu.to(udt), gv.to(vdt), torch.from_numpy(gm).to(mdev, mdt),
+                torch.from_numpy(np.ascontiguousarray(gs)).to(sdev, sdt), None, None, None, None)

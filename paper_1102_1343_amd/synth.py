@@ -333,3 +333,29 @@ def ensemble(ndom=256, side_min=256, side_max=1024, steps=500, dt=0.25, seed=SEE
                                 boundary_policy=1, guard_width=1),
                            name=f"ens{k}_{n}"))
     return out
+
+
+def adjoint_case(n=1024, steps=500, dt=0.25, seed=SEED, field_dtype=np.float64):
+    """Adjoint workload: n x n patchy landscape (13 Voronoi fuel categories,
+    8 hills, 16-mode Fourier wind, dx = 6 m) with two instant circular
+    ignitions of radius 3 dx at t = 0, centres uniform in the central half;
+    ``steps`` steps of dt.  Returns (problem, perturbation), the perturbation
+    defining the target run: multipliers U[0.8, 1.2] per category, wind x1.1,
+    each centre shifted by 2 cells in a random direction."""
+    rng = np.random.default_rng([seed, 5])
+    dx = 6.0
+    fuels = random_fuels(np.random.default_rng(seed))
+    cat = voronoi_categories(rng, n, n)
+    gzx, gzy = hills_gradient(rng, n, n, dx, dx, dtype=field_dtype)
+    ign = []
+    for _ in range(2):
+        cx, cy = rng.uniform(0.3, 0.7, 2) * n * dx
+        ign.append(ignition(cx, cy, t_start=0.0, radius=3 * dx, ros=math.inf))
+    wind = fourier_wind(rng, n, n, dx, dx, dtype=field_dtype)
+    prob = Problem(n, n, dx, dx, 10, 10, fuels, cat, gzx, gzy, ign, dt, steps, [wind], 0,
+                   dict(viscosity=0.4, viscosity_mode=0, ros_cap=6.0, boundary_policy=1,
+                        guard_width=1), name=f"adjoint{n}")
+    ang = rng.uniform(0, 2 * math.pi, 2)
+    pert = dict(mult=rng.uniform(0.8, 1.2, len(fuels)), wind_scale=1.1,
+                shift=[(2 * dx * math.cos(a), 2 * dx * math.sin(a)) for a in ang])
+    return prob, pert

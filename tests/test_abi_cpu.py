@@ -67,7 +67,7 @@ def test_state_bytes_and_errors_without_gpu(lib):
         assert lib.fire_state_bytes(C.byref(bad), 13) == 0
     assert lib.fire_state_bytes(C.byref(m), 0) == 0
     assert lib.fire_state_bytes(C.byref(m), 257) == 0
-    assert lib.fire_abi_version() == 2
+    assert lib.fire_abi_version() == 3
     assert lib.fire_strerror(-4) == b"fire reached the domain boundary guard ring"
     assert lib.fire_strerror(0) == b"ok"
     # argument errors are reported before any device work
@@ -110,3 +110,21 @@ def test_ensemble_layout_and_errors_without_gpu(lib):
                              None, None, C.c_size_t(0), None) == -1
     assert lib.fire_ens_step(None, None, None, C.c_double(0.5), None, None) == -1
     assert lib.fire_ens_status(None, None) == -1
+
+
+def test_adjoint_sizes_and_errors_without_gpu(lib):
+    from paper_1102_1343_amd import fire as F
+    lib.fire_adj_bytes.restype = C.c_size_t
+    m = F.fire_mesh(100, 80, 6.0, 6.0, 10, 10, F.FIRE_F32, 0)
+    n = 100 * 80
+    nb = lib.fire_adj_bytes(C.byref(m), 13, 500, 50)
+    # 10 checkpoints + 51 stack levels of psi, plus the working arrays
+    assert nb >= (10 + 51) * 4 * n
+    assert nb <= (10 + 51 + 40) * 8 * n
+    assert lib.fire_adj_bytes(C.byref(m), 13, 0, 50) == 0
+    assert lib.fire_adj_bytes(C.byref(m), 13, 500, 0) == 0
+    assert lib.fire_adj_bytes(C.byref(m), 0, 500, 50) == 0
+    h = C.c_void_p()
+    assert lib.fire_adj_init(C.byref(h), None, 10, 5, None, C.c_size_t(0)) == -1
+    assert lib.fire_adj_forward(None, None, None, C.c_double(0.25)) == -1
+    assert lib.fire_adj_backward(None, None, None, None, None, None) == -1

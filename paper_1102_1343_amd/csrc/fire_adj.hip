@@ -21,11 +21,14 @@
 // rate, ghost formula, ignition minimum, crossing step, sub-cell signs) is
 // taken where the forward took it, and the derivative is that of the branch.
 //
-// The reverse kernels work on ghost-extended arrays ((nx+2) x (ny+2) nodes,
-// one extrapolated ring) so that the stencil transposes need no boundary
-// cases: a cell writes its five weighted partials, every extended node
-// gathers the ones aimed at it in a fixed order, and the transpose of G
-// moves ghost adjoints onto the interior nodes they were extrapolated from.
+// The segment replay also records psi' and psi* of every step.  A reversed
+// step is then three passes over the nodes: (1) the ignition times set in
+// the step and the stage-2 partials, (2) their gather and the stage-1
+// partials, (3) their gather and the ignition minimum.  A cell writes its
+// five weighted stencil partials; every node gathers the ones aimed at it in
+// a fixed order, plus its share of the side ghosts extrapolated from it (the
+// transpose of G).  The final-time fuel fraction is reversed once, on
+// ghost-extended arrays (its stencil reaches the corners).
 // Gradients accumulate per cell in double and are reduced in a fixed order:
 // results are bitwise reproducible and independent of K.
 #include <cmath>
@@ -44,7 +47,7 @@ constexpr int kAB = 256;          // threads per block of the adjoint kernels
 constexpr int kShift = 2 * FIRE_MAX_IGNITIONS;
 
 struct AdjArgs {
-    int32_t nx, ny, ncat, nign, visc_mode, pad;
+    int32_t nx, ny, ncat, nign, visc_mode, ign_active;   // ign_active: some ignition at t
     double dx, dy, rdx, rdy, eps, cap, t, dt;
 };
 
@@ -226,41 +229,6 @@ __device__ __forceinline__ void shift_reduce(int g, double cx, double cy, int ni
 
 // ---------------------------------------------------------------- kernels
 
-// psi' = min(psi, psi_g) over the active ignitions (as the step kernel does),
-// the ignition that set the minimum, and for a node lit in this step the
-// ignition whose arrival time it takes.
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_adj_ignite(const AdjArgs a, const fire_ignition *ign, const T *psi, T *p0, int8_t *sel,
-             int8_t *tsel) {
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= a.nx * a.ny) return;
-    const int x = i % a.nx, y = i / a.nx;
-    T p = psi[i];
-    const T pold = p;
-    T tig = M<T>::inf();
-    int sg = -1, tg = -1;
-    const double xg = ((double)x + 0.5) * a.dx, yg = ((double)y + 0.5) * a.dy;
-    for (int g = 0; g < a.nign; g++) {
-        IgnGeo<T> geo;
-        if (!ign_setup<T>(ign[g], a.t, geo)) continue;
-        T arr;
-        const T pg = ign_psi(geo, T(xg - geo.ax), T(yg - geo.ay), arr);
-        if (pg <= T(0) && arr < tig) {
-            tig = arr;
-            tg = g;
-        }
-        if (pg < p) {
-            p = pg;
-            sg = g;
-        }
-    }
-    if (!(pold > T(0) && p <= T(0))) tg = -1;
-    p0[i] = p;
-    sel[i] = (int8_t)sg;
-    tsel[i] = (int8_t)tg;
-}
-
 // Extended copy with the ghost ring of Sect. 4.1 (corners: x extrapolation
 // of the ghost row), as the step kernel fills it.
 template <typename T>
@@ -295,132 +263,6 @@ template <typename T> __device__ __forceinline__ Consts<T> consts(const AdjArgs 
     c.cap = T(a.cap);
     c.visc_mode = a.visc_mode;
     return c;
-}
-
-// psi* = psi' + dt F(G psi') on the interior nodes (stage 1 of Eq. 11).
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_adj_stage(const AdjArgs a, const T *E, const T *p0, const T *u, const T *v, const T *gzx,
-            const T *gzy, const uint8_t *cat, const T *coef, T *out) {
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= a.nx * a.ny) return;
-    const int x = i % a.nx, y = i / a.nx;
-    alignas(16) T row[kLRow];
-    load_row(coef, cat[i], a.ncat, row);
-    const int c = ext_idx(a, x, y), ex = a.nx + 2;
-    const T F = rhs5(E[c], E[c - 1], E[c + 1], E[c - ex], E[c + ex], u[i], v[i], gzx[i], gzy[i],
-                     row, consts<T>(a));
-    out[i] = p0[i] + T(a.dt) * F;
-}
-
-// Ignition times set in step n (set_step == n): a crossing node (psi' > 0)
-// passes dL/dt_i to psi' and psi^{n+1} through Eq. (14); a node lit by an
-// ignition passes it to that ignition's shift through the arrival time.
-// dL/dt_i is then cleared (before the step t_i was +inf).
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_adj_cross(const AdjArgs a, int n, const int32_t *set_step, const T *p0, const T *pn1, T *L1,
-            T *LT, T *LP0, const int8_t *tsel, const fire_ignition *ign, double *acc) {
-    __shared__ double sh[kAB];
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    int g = -1;
-    double cx = 0.0, cy = 0.0;
-    if (i < a.nx * a.ny) {
-        T lp0 = T(0);
-        if (set_step[i] == n) {
-            const T lt = LT[i];
-            LT[i] = T(0);
-            const T p = p0[i], q = pn1[i];
-            if (p > T(0)) {
-                const T D = p - q;
-                const T dt = T(a.dt);
-                const T iD2 = M<T>::div(T(1), D * D);
-                L1[i] += lt * dt * p * iD2;
-                lp0 = -lt * dt * q * iD2;
-            } else if (tsel[i] >= 0 && lt != T(0)) {
-                const int k = tsel[i];
-                IgnGeo<T> geo;
-                if (ign_setup<T>(ign[k], a.t, geo)) {
-                    const int x = i % a.nx, y = i / a.nx;
-                    const T px = T(((double)x + 0.5) * a.dx - geo.ax);
-                    const T py = T(((double)y + 0.5) * a.dy - geo.ay);
-                    T s = (px * geo.ex + py * geo.ey) * geo.invL2;
-                    const bool sfree = s > T(0) && s < T(1);
-                    s = vmin(vmax(s, T(0)), T(1));
-                    const T qx = px - s * geo.ex, qy = py - s * geo.ey;
-                    const T d = M<T>::sqrt(qx * qx + qy * qy);
-                    const T arr = geo.tg + s * geo.lenv + d * geo.invS;
-                    if (arr < geo.t) {
-                        // translation by delta moves the node by -delta relative to the segment
-                        T ax_ = T(0), ay_ = T(0);
-                        if (d > T(0)) {
-                            ax_ = -geo.invS * M<T>::div(qx, d);
-                            ay_ = -geo.invS * M<T>::div(qy, d);
-                        }
-                        if (sfree) {
-                            ax_ -= geo.lenv * geo.ex * geo.invL2;
-                            ay_ -= geo.lenv * geo.ey * geo.invL2;
-                        }
-                        g = k;
-                        cx = (double)(lt * ax_);
-                        cy = (double)(lt * ay_);
-                    }
-                }
-            }
-        }
-        LP0[i] = lp0;
-    }
-    shift_reduce(g, cx, cy, a.nign, acc, sh);
-}
-
-// Cell i of a stage: q = w lambda_i; the five weighted partials of F_i go to
-// D (planes c, w, e, s, n); dL/du, dL/dv, dL/dm accumulate per cell.
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_adj_rhs(const AdjArgs a, const T *E, const T *lam, T w, const T *u, const T *v, const T *gzx,
-          const T *gzy, const uint8_t *cat, const T *coef, T *D, double *gu, double *gv,
-          double *gm) {
-    const int n = a.nx * a.ny;
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= n) return;
-    const T q = w * lam[i];
-    if (q == T(0)) {
-#pragma unroll
-        for (int k = 0; k < 5; k++) D[(size_t)k * n + i] = T(0);
-        return;
-    }
-    const int x = i % a.nx, y = i / a.nx;
-    const int cv = cat[i] < a.ncat - 1 ? cat[i] : a.ncat - 1;
-    alignas(16) T row[kLRow];
-    make_row(coef + cv * kNCoef, row);
-    const int c = ext_idx(a, x, y), ex = a.nx + 2;
-    const RhsGrad<T> r = rhs5_grad(E[c], E[c - 1], E[c + 1], E[c - ex], E[c + ex], u[i], v[i],
-                                   gzx[i], gzy[i], row, coef + cv * kNCoef, consts<T>(a));
-    D[i] = q * r.dc;
-    D[(size_t)n + i] = q * r.dw;
-    D[(size_t)2 * n + i] = q * r.de;
-    D[(size_t)3 * n + i] = q * r.ds;
-    D[(size_t)4 * n + i] = q * r.dn;
-    gu[i] += (double)(q * r.du);
-    gv[i] += (double)(q * r.dv);
-    gm[i] += (double)(q * r.dm);
-}
-
-// Extended node j collects the partials aimed at it, in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(kAB) k_adj_gather(const AdjArgs a, const T *D, T *LE) {
-    const int ex = a.nx + 2, ey = a.ny + 2, n = a.nx * a.ny;
-    const int j = blockIdx.x * kAB + threadIdx.x;
-    if (j >= ex * ey) return;
-    const int x = j % ex - 1, y = j / ex - 1;
-    auto in = [&](int xx, int yy) { return xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny; };
-    T s = T(0);
-    if (in(x, y)) s += D[y * a.nx + x];
-    if (in(x + 1, y)) s += D[(size_t)n + y * a.nx + x + 1];          // east cell's west node
-    if (in(x - 1, y)) s += D[(size_t)2 * n + y * a.nx + x - 1];      // west cell's east node
-    if (in(x, y + 1)) s += D[(size_t)3 * n + (y + 1) * a.nx + x];    // north cell's south node
-    if (in(x, y - 1)) s += D[(size_t)4 * n + (y - 1) * a.nx + x];    // south cell's north node
-    LE[j] = s;
 }
 
 // Corner ghosts (x extrapolation of the ghost row) hand their adjoint to the
@@ -477,41 +319,305 @@ k_adj_ghostT(const AdjArgs a, const T *src, const T *LE, const T *b1, const T *b
     out[i] = s;
 }
 
-// Transpose of the ignition minimum: dL/dpsi^n where no ignition set the
-// minimum; else the ignition's shift gets dL/dpsi' d(psi_g)/d(shift).
+
+// ---- fused reverse step: node values with the side ghosts of Sect. 4.1
+// formed inline (a five-point stencil of an interior cell never reaches a
+// corner), and the gather of stage partials with the transpose of those
+// ghosts, in the same order as the extended-array kernels above.
+
+template <typename T>
+__device__ __forceinline__ T node_g(const AdjArgs &a, const T *P, int x, int y) {
+    const int nx = a.nx, ny = a.ny;
+    if (x < 0) return ghost(P[y * nx], P[y * nx + 1]);
+    if (x >= nx) return ghost(P[y * nx + nx - 1], P[y * nx + nx - 2]);
+    if (y < 0) return ghost(P[x], P[nx + x]);
+    if (y >= ny) return ghost(P[(ny - 1) * nx + x], P[(ny - 2) * nx + x]);
+    return P[y * nx + x];
+}
+
+// Sum of the stage partials (planes c, w, e, s, n of D) aimed at interior
+// node (x, y), plus its share of the side ghosts extrapolated from it.  A
+// cell whose adjoint weight W is zero wrote no partials (they are zero), so
+// they are read only where W != 0.
+template <typename T>
+__device__ __forceinline__ T gather_node(const AdjArgs &a, const T *D, const T *W, const T *P,
+                                         int x, int y) {
+    const int nx = a.nx, ny = a.ny;
+    const size_t n = (size_t)nx * ny;
+    const int i = y * nx + x;
+    T s = T(0);
+    if (W[i] != T(0)) s += D[i];
+    if (x + 1 < nx && W[i + 1] != T(0)) s += D[n + i + 1];
+    if (x - 1 >= 0 && W[i - 1] != T(0)) s += D[2 * n + i - 1];
+    if (y + 1 < ny && W[i + nx] != T(0)) s += D[3 * n + i + nx];
+    if (y - 1 >= 0 && W[i - nx] != T(0)) s += D[4 * n + i - nx];
+    T dp, dq;
+    if (x <= 1 && W[y * nx] != T(0)) {
+        dghost(P[y * nx], P[y * nx + 1], dp, dq);
+        s += D[n + y * nx] * (x == 0 ? dp : dq);
+    }
+    if (x >= nx - 2 && W[y * nx + nx - 1] != T(0)) {
+        dghost(P[y * nx + nx - 1], P[y * nx + nx - 2], dp, dq);
+        s += D[2 * n + y * nx + nx - 1] * (x == nx - 1 ? dp : dq);
+    }
+    if (y <= 1 && W[x] != T(0)) {
+        dghost(P[x], P[nx + x], dp, dq);
+        s += D[3 * n + x] * (y == 0 ? dp : dq);
+    }
+    if (y >= ny - 2 && W[(ny - 1) * nx + x] != T(0)) {
+        dghost(P[(ny - 1) * nx + x], P[(ny - 2) * nx + x], dp, dq);
+        s += D[4 * n + (ny - 1) * nx + x] * (y == ny - 1 ? dp : dq);
+    }
+    return s;
+}
+
+// Derivatives of stage F at cell i on level set P (side ghosts inline).
+template <typename T>
+__device__ __forceinline__ RhsGrad<T> stage_grad(const AdjArgs &a, const T *P, int x, int y,
+                                                 const T *u, const T *v, const T *gzx,
+                                                 const T *gzy, const uint8_t *cat,
+                                                 const T *coef) {
+    const int i = y * a.nx + x;
+    const int cv = cat[i] < a.ncat - 1 ? cat[i] : a.ncat - 1;
+    alignas(16) T row[kLRow];
+    make_row(coef + cv * kNCoef, row);
+    return rhs5_grad(P[i], node_g(a, P, x - 1, y), node_g(a, P, x + 1, y), node_g(a, P, x, y - 1),
+                     node_g(a, P, x, y + 1), u[i], v[i], gzx[i], gzy[i], row, coef + cv * kNCoef,
+                     consts<T>(a));
+}
+
+// The five stencil partials of stage F at cell i weighted by q = w lam, into
+// D.  Nothing is written where lam = 0 (the gathers skip such cells).
+template <typename T>
+__device__ __forceinline__ void stage_D(const RhsGrad<T> &r, int i, size_t n, T q, T *D) {
+    D[i] = q * r.dc;
+    D[n + i] = q * r.dw;
+    D[2 * n + i] = q * r.de;
+    D[3 * n + i] = q * r.ds;
+    D[4 * n + i] = q * r.dn;
+}
+
+// Ignition state of node (x, y) at the start of a step: psi' = min over the
+// active ignitions (the last one lowering it is `sel`), and the ignition
+// whose arrival time a node lit in this step takes (`tsel`).
+template <typename T>
+__device__ __forceinline__ void ignite_node(const AdjArgs &a, const fire_ignition *ign, T psi,
+                                            int x, int y, int &sel, int &tsel) {
+    T p = psi;
+    const T pold = p;
+    T tig = M<T>::inf();
+    sel = tsel = -1;
+    const double xg = ((double)x + 0.5) * a.dx, yg = ((double)y + 0.5) * a.dy;
+    for (int g = 0; g < a.nign; g++) {
+        IgnGeo<T> geo;
+        if (!ign_setup<T>(ign[g], a.t, geo)) continue;
+        T arr;
+        const T pg = ign_psi(geo, T(xg - geo.ax), T(yg - geo.ay), arr);
+        if (pg <= T(0) && arr < tig) {
+            tig = arr;
+            tsel = g;
+        }
+        if (pg < p) {
+            p = pg;
+            sel = g;
+        }
+    }
+    if (!(pold > T(0) && p <= T(0))) tsel = -1;
+}
+
+// Reverse, part 1 at node i for step n: the ignition time set in the step
+// (Eq. 14 for a crossing node, the arrival time for a node lit by an
+// ignition) passes dL/dt_i on; then the stage-2 partials weighted by
+// dt/2 dL/dpsi^{n+1}.  Returns dL/dpsi^{n+1} with the crossing part added.
+template <typename T>
+__device__ __forceinline__ T rev1_node(const AdjArgs &a, int n, int i, int x, int y, T lam,
+                                       const int32_t *set_step, const T *psi_n, const T *P0,
+                                       const T *B, const T *pn1, T *LT, T *LP0, const T *u,
+                                       const T *v, const T *gzx, const T *gzy,
+                                       const uint8_t *cat, const T *coef,
+                                       const fire_ignition *ign, T *D, int &g, double &cx,
+                                       double &cy) {
+    T lp0 = T(0);
+    if (set_step[i] == n) {
+        const T lt = LT[i];
+        LT[i] = T(0);
+        const T p = P0[i], q = pn1[i];
+        if (p > T(0)) {
+            const T D2 = (p - q) * (p - q);
+            const T dt = T(a.dt);
+            const T iD2 = M<T>::div(T(1), D2);
+            lam += lt * dt * p * iD2;
+            lp0 = -lt * dt * q * iD2;
+        } else if (lt != T(0)) {
+            int sg, k;
+            ignite_node(a, ign, psi_n[i], x, y, sg, k);
+            IgnGeo<T> geo;
+            if (k >= 0 && ign_setup<T>(ign[k], a.t, geo)) {
+                const T px = T(((double)x + 0.5) * a.dx - geo.ax);
+                const T py = T(((double)y + 0.5) * a.dy - geo.ay);
+                T s = (px * geo.ex + py * geo.ey) * geo.invL2;
+                const bool sfree = s > T(0) && s < T(1);
+                s = vmin(vmax(s, T(0)), T(1));
+                const T qx = px - s * geo.ex, qy = py - s * geo.ey;
+                const T d = M<T>::sqrt(qx * qx + qy * qy);
+                const T arr = geo.tg + s * geo.lenv + d * geo.invS;
+                if (arr < geo.t) {
+                    // translating the ignition by delta moves the node by -delta
+                    T ax_ = T(0), ay_ = T(0);
+                    if (d > T(0)) {
+                        ax_ = -geo.invS * M<T>::div(qx, d);
+                        ay_ = -geo.invS * M<T>::div(qy, d);
+                    }
+                    if (sfree) {
+                        ax_ -= geo.lenv * geo.ex * geo.invL2;
+                        ay_ -= geo.lenv * geo.ey * geo.invL2;
+                    }
+                    g = k;
+                    cx = (double)(lt * ax_);
+                    cy = (double)(lt * ay_);
+                }
+            }
+        }
+    }
+    LP0[i] = lp0;
+    if (lam != T(0))
+        stage_D(stage_grad(a, B, x, y, u, v, gzx, gzy, cat, coef), i, (size_t)a.nx * a.ny,
+                T(0.5) * T(a.dt) * lam, D);
+    return lam;
+}
+
+// Reverse, part 3 at node i for step n: dL/dpsi' = crossing part +
+// dL/dpsi^{n+1}/2 + dL/dpsi* + (stage-1 partials gathered through the ghosts
+// of psi'), then through the ignition minimum: returns dL/dpsi^n (zero where
+// an ignition set psi', whose shift gets the contribution instead).
+template <typename T>
+__device__ __forceinline__ T rev3_node(const AdjArgs &a, int i, int x, int y, T l1, const T *D1,
+                                       const T *P0, const T *LP0, const T *LB, const T *psi_n,
+                                       const fire_ignition *ign, int &g, double &cx,
+                                       double &cy) {
+    T l = gather_node(a, D1, LB, P0, x, y);
+    l += LP0[i];
+    l += T(0.5) * l1;
+    l += LB[i];
+    int sg = -1, tg;
+    if (a.ign_active) ignite_node(a, ign, psi_n[i], x, y, sg, tg);
+    if (sg < 0) return l;
+    IgnGeo<T> geo;
+    if (l != T(0) && ign_setup<T>(ign[sg], a.t, geo)) {
+        const T px = T(((double)x + 0.5) * a.dx - geo.ax);
+        const T py = T(((double)y + 0.5) * a.dy - geo.ay);
+        T s = (px * geo.ex + py * geo.ey) * geo.invL2;
+        s = vmin(vmax(s, T(0)), T(1));
+        const T qx = px - s * geo.ex, qy = py - s * geo.ey;
+        const T d = M<T>::sqrt(qx * qx + qy * qy);
+        if (d > T(0)) {
+            g = sg;
+            cx = (double)(-l * M<T>::div(qx, d));
+            cy = (double)(-l * M<T>::div(qy, d));
+        }
+    }
+    return T(0);
+}
+
+// Part 1 of step n alone (the last step of a segment).
 template <typename T>
 __global__ void __launch_bounds__(kAB)
-k_adj_ignT(const AdjArgs a, const T *LP0, const int8_t *sel, const fire_ignition *ign, T *L1,
-           double *acc) {
+k_rev_stage2(const AdjArgs a, int n, const int32_t *set_step, const T *psi_n, const T *P0,
+             const T *B, const T *pn1, T *L1, T *LT, T *LP0, const T *u, const T *v,
+             const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
+             const fire_ignition *ign, T *D, double *acc) {
     __shared__ double sh[kAB];
     const int i = blockIdx.x * kAB + threadIdx.x;
     int g = -1;
     double cx = 0.0, cy = 0.0;
     if (i < a.nx * a.ny) {
-        const T l = LP0[i];
-        const int k = sel[i];
-        if (k < 0) {
-            L1[i] = l;
-        } else {
-            L1[i] = T(0);
-            IgnGeo<T> geo;
-            if (l != T(0) && ign_setup<T>(ign[k], a.t, geo)) {
-                const int x = i % a.nx, y = i / a.nx;
-                const T px = T(((double)x + 0.5) * a.dx - geo.ax);
-                const T py = T(((double)y + 0.5) * a.dy - geo.ay);
-                T s = (px * geo.ex + py * geo.ey) * geo.invL2;
-                s = vmin(vmax(s, T(0)), T(1));
-                const T qx = px - s * geo.ex, qy = py - s * geo.ey;
-                const T d = M<T>::sqrt(qx * qx + qy * qy);
-                if (d > T(0)) {
-                    g = k;
-                    cx = (double)(-l * M<T>::div(qx, d));
-                    cy = (double)(-l * M<T>::div(qy, d));
-                }
-            }
-        }
+        const int x = i % a.nx, y = i / a.nx;
+        const T l = L1[i];
+        const T lam = rev1_node(a, n, i, x, y, l, set_step, psi_n, P0, B, pn1, LT, LP0, u, v, gzx,
+                                gzy, cat, coef, ign, D, g, cx, cy);
+        if (set_step[i] == n) L1[i] = lam;
     }
     shift_reduce(g, cx, cy, a.nign, acc, sh);
+}
+
+// Reverse, part 2: dL/dpsi* = dL/dpsi^{n+1}/2 + (stage-2 partials gathered
+// through the ghosts of psi*), then the stage-1 partials weighted by
+// dt dL/dpsi*.
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_rev_stage1(const AdjArgs a, const T *D, const T *B, const T *L1, T *LB, const T *P0,
+             const T *u, const T *v, const T *gzx, const T *gzy, const uint8_t *cat,
+             const T *coef, T *D1, double *gu, double *gv, double *gm) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    const T l1 = L1[i];
+    T lb = gather_node(a, D, L1, B, x, y);
+    lb += T(0.5) * l1;
+    LB[i] = lb;
+    if (l1 == T(0) && lb == T(0)) return;
+    // wind and multiplier partials of both stages, one update per cell:
+    // stage 2 (weight dt/2 lam^{n+1}, recomputed), then stage 1 (dt lam*)
+    double du = gu[i], dv = gv[i], dm = gm[i];
+    if (l1 != T(0)) {
+        const RhsGrad<T> r2 = stage_grad(a, B, x, y, u, v, gzx, gzy, cat, coef);
+        const T q2 = T(0.5) * T(a.dt) * l1;
+        du += (double)(q2 * r2.du);
+        dv += (double)(q2 * r2.dv);
+        dm += (double)(q2 * r2.dm);
+    }
+    if (lb != T(0)) {
+        const RhsGrad<T> r1 = stage_grad(a, P0, x, y, u, v, gzx, gzy, cat, coef);
+        const T q1 = T(a.dt) * lb;
+        stage_D(r1, i, (size_t)a.nx * a.ny, q1, D1);
+        du += (double)(q1 * r1.du);
+        dv += (double)(q1 * r1.dv);
+        dm += (double)(q1 * r1.dm);
+    }
+    gu[i] = du;
+    gv[i] = dv;
+    gm[i] = dm;
+}
+
+// Part 3 of step n alone (the first step of a segment).
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_rev_psi(const AdjArgs a, const T *D1, const T *P0, const T *LP0, const T *LB, const T *psi_n,
+          const fire_ignition *ign, T *L1, double *acc) {
+    __shared__ double sh[kAB];
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    int g = -1;
+    double cx = 0.0, cy = 0.0;
+    if (i < a.nx * a.ny) {
+        const int x = i % a.nx, y = i / a.nx;
+        L1[i] = rev3_node(a, i, x, y, L1[i], D1, P0, LP0, LB, psi_n, ign, g, cx, cy);
+    }
+    shift_reduce(g, cx, cy, a.nign, acc, sh);
+}
+
+// Part 3 of step n (args a3) fused with part 1 of step n - 1 (args a1) at
+// the same node: both are per-node given the gathers' inputs.
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_rev_psi_stage2(const AdjArgs a3, const AdjArgs a1, int n1, const T *D1, const T *P0n,
+                 T *LP0, const T *LB, const T *psi_n, const int32_t *set_step,
+                 const T *psi_n1, const T *P0n1, const T *Bn1, T *L1, T *LT, const T *u,
+                 const T *v, const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
+                 const fire_ignition *ign, T *D, double *acc) {
+    __shared__ double sh[kAB];
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    int g3 = -1, g1 = -1;
+    double cx3 = 0.0, cy3 = 0.0, cx1 = 0.0, cy1 = 0.0;
+    if (i < a3.nx * a3.ny) {
+        const int x = i % a3.nx, y = i / a3.nx;
+        // step n: dL/dpsi^n (psi^n is the state after step n - 1)
+        const T l = rev3_node(a3, i, x, y, L1[i], D1, P0n, LP0, LB, psi_n, ign, g3, cx3, cy3);
+        // step n - 1, whose output psi^n is psi_n
+        L1[i] = rev1_node(a1, n1, i, x, y, l, set_step, psi_n1, P0n1, Bn1, psi_n, LT, LP0, u, v,
+                          gzx, gzy, cat, coef, ign, D, g1, cx1, cy1);
+    }
+    shift_reduce(g3, cx3, cy3, a3.nign, acc, sh);
+    shift_reduce(g1, cx1, cy1, a1.nign, acc, sh);
 }
 
 // Node times t^ on the extended mesh: t' where psi >= 0 and on the ghosts,
@@ -626,12 +732,15 @@ k_cat_partial(const double *gm, const uint8_t *cat, int cnt, int ncat, double *p
     }
 }
 
-__global__ void k_col_sum(const double *part, int rows, int cols, double *out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= cols) return;
+// out[k] = sum over rows of part[row][k]: one block per column, fixed order.
+__global__ void __launch_bounds__(kAB)
+k_col_sum(const double *part, int rows, int cols, double *out) {
+    __shared__ double sh[kAB];
+    const int k = blockIdx.x;
     double s = 0.0;
-    for (int r = 0; r < rows; r++) s += part[(size_t)r * cols + k];
-    out[k] = s;
+    for (int r = threadIdx.x; r < rows; r += kAB) s += part[(size_t)r * cols + k];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[k] = s;
 }
 
 // ---------------------------------------------------------------- host side
@@ -639,8 +748,8 @@ __global__ void k_col_sum(const double *part, int rows, int cols, double *out) {
 int hip_fail(hipError_t e) { return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP; }
 
 struct AdjLayout {
-    size_t ckpt, stack, set_step, tig, frac, flux, status, p0, b, e1, e2, le, th, sel, tsel, l1,
-        lt, lp0, lb, d, gu, gv, gm, acc, part, small, total;
+    size_t ckpt, stack, rp0, rb, set_step, tig, frac, flux, status, e1, e2, le, th, l1, lt, lp0,
+        lb, d, d1, gu, gv, gm, acc, part, small, total;
 };
 
 }  // namespace
@@ -676,24 +785,23 @@ AdjLayout adj_layout(const fire_mesh *m, int ncat, int nsteps, int every) {
     };
     take(L.ckpt, (size_t)nseg * n * es);
     take(L.stack, (size_t)(every + 1) * n * es);
+    take(L.rp0, (size_t)every * n * es);
+    take(L.rb, (size_t)every * n * es);
     take(L.set_step, n * 4);
     take(L.tig, n * es);
     take(L.frac, n * es);
     take(L.flux, 2 * natm * es);
     take(L.status, 64);
-    take(L.p0, n * es);
-    take(L.b, n * es);
     take(L.e1, ne * es);
     take(L.e2, ne * es);
     take(L.le, ne * es);
     take(L.th, ne * es);
-    take(L.sel, n);
-    take(L.tsel, n);
     take(L.l1, n * es);
     take(L.lt, n * es);
     take(L.lp0, n * es);
     take(L.lb, n * es);
     take(L.d, 5 * n * es);
+    take(L.d1, 5 * n * es);
     take(L.gu, n * 8);
     take(L.gv, n * 8);
     take(L.gm, n * 8);
@@ -715,12 +823,25 @@ template <typename T> struct Run {
     template <typename P> P *at(size_t off) { return reinterpret_cast<P *>(A->arena + off); }
     T *arr(size_t off) { return at<T>(off); }
     T *stack(int k) { return arr(A->L.stack) + (size_t)k * n; }
+    T *rp0(int k) { return arr(A->L.rp0) + (size_t)k * n; }   // psi' of step k
+    T *rb(int k) { return arr(A->L.rb) + (size_t)k * n; }     // psi* of step k
     const T *coef() { return reinterpret_cast<const T *>(c->arena + c->off_coef); }
     const fire_ignition *ign() {
         return reinterpret_cast<const fire_ignition *>(c->arena + c->off_ign);
     }
     const T *cur_psi() { return reinterpret_cast<const T *>(c->arena + c->off_psi[c->cur]); }
     const T *tign_final() { return reinterpret_cast<const T *>(c->arena + c->off_tign); }
+    // whether any ignition is active at time t (the test of ign_setup)
+    int ign_active_at(double t) const {
+        for (int g = 0; g < c->nign; g++) {
+            const fire_ignition &q = c->ign[g];
+            const bool torch = q.vx != 0.0 || q.vy != 0.0;
+            const double tend = torch ? q.t_end : q.t_start;
+            const double grow = std::isinf(q.ros) ? 0.0 : q.radius / q.ros;
+            if (t >= q.t_start && t <= tend + grow) return 1;
+        }
+        return 0;
+    }
 
     explicit Run(fire_adj *A_) : A(A_), c(A_->c), s(A_->c->stream) {
         const fire_mesh &m = c->mesh;
@@ -781,48 +902,49 @@ template <typename T> struct Run {
         for (int k = s0; k < s1; k++) {
             h = step_raw(c, stack(k - s0), stack(k - s0 + 1), arr(A->L.tig), arr(A->L.frac), A->u,
                          A->v, A->tstep[k], A->dt, arr(A->L.flux), arr(A->L.flux) + natm,
-                         at<int>(A->L.status));
+                         at<int>(A->L.status), rp0(k - s0), rb(k - s0));
             if (h != hipSuccess) return h;
         }
         return hipGetLastError();
     }
 
-    hipError_t reverse_step(int n_, int k) {
-        a.t = A->tstep[n_];
-        const T *psi_n = stack(k), *psi_n1 = stack(k + 1);
+    // Reverse the steps of one replayed segment [s0, s1): part 1 of the last
+    // step, then per step part 2 and part 3 fused with part 1 of the step
+    // before it (part 3 alone for the first step of the segment).
+    hipError_t reverse_segment(int s0, int s1) {
         const T *u = (const T *)A->u, *v = (const T *)A->v;
         const T *gx = (const T *)c->dzdx, *gy = (const T *)c->dzdy;
-        T *P0 = arr(A->L.p0), *B = arr(A->L.b), *E1 = arr(A->L.e1), *E2 = arr(A->L.e2);
-        T *LE = arr(A->L.le), *L1 = arr(A->L.l1), *LT = arr(A->L.lt), *LP0 = arr(A->L.lp0);
-        T *LB = arr(A->L.lb), *D = arr(A->L.d);
+        T *L1 = arr(A->L.l1), *LT = arr(A->L.lt), *LP0 = arr(A->L.lp0), *LB = arr(A->L.lb);
+        T *D = arr(A->L.d), *D1 = arr(A->L.d1);
         double *gu = at<double>(A->L.gu), *gv = at<double>(A->L.gv), *gm = at<double>(A->L.gm);
         double *acc = at<double>(A->L.acc);
-        int8_t *sel = at<int8_t>(A->L.sel), *tsel = at<int8_t>(A->L.tsel);
-        const T dt = T(A->dt);
-        // recompute the step's intermediate states
-        hipLaunchKernelGGL(k_adj_ignite<T>, dim3(gn), dim3(kAB), 0, s, a, ign(), psi_n, P0, sel,
-                           tsel);
-        hipLaunchKernelGGL(k_ext<T>, dim3(ge), dim3(kAB), 0, s, a, P0, E1);
-        hipLaunchKernelGGL(k_adj_stage<T>, dim3(gn), dim3(kAB), 0, s, a, E1, P0, u, v, gx, gy,
-                           c->cat, coef(), B);
-        hipLaunchKernelGGL(k_ext<T>, dim3(ge), dim3(kAB), 0, s, a, B, E2);
-        // ignition times set in this step
-        hipLaunchKernelGGL(k_adj_cross<T>, dim3(gn), dim3(kAB), 0, s, a, n_,
-                           at<int32_t>(A->L.set_step), P0, psi_n1, L1, LT, LP0, tsel, ign(), acc);
-        // stage 2: psi^{n+1} = (psi' + psi*)/2 + dt/2 F(G psi*)
-        hipLaunchKernelGGL(k_adj_rhs<T>, dim3(gn), dim3(kAB), 0, s, a, E2, L1, T(0.5) * dt, u, v,
-                           gx, gy, c->cat, coef(), D, gu, gv, gm);
-        hipLaunchKernelGGL(k_adj_gather<T>, dim3(ge), dim3(kAB), 0, s, a, D, LE);
-        hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, B, LE,
-                           (const T *)nullptr, L1, T(0.5), (const T *)nullptr, LB);
-        // stage 1: psi* = psi' + dt F(G psi')
-        hipLaunchKernelGGL(k_adj_rhs<T>, dim3(gn), dim3(kAB), 0, s, a, E1, LB, dt, u, v, gx, gy,
-                           c->cat, coef(), D, gu, gv, gm);
-        hipLaunchKernelGGL(k_adj_gather<T>, dim3(ge), dim3(kAB), 0, s, a, D, LE);
-        hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, P0, LE, LP0, L1,
-                           T(0.5), LB, LP0);
-        // ignition minimum
-        hipLaunchKernelGGL(k_adj_ignT<T>, dim3(gn), dim3(kAB), 0, s, a, LP0, sel, ign(), L1, acc);
+        const int32_t *set_step = at<int32_t>(A->L.set_step);
+        AdjArgs an = a;
+        an.t = A->tstep[s1 - 1];
+        an.ign_active = ign_active_at(an.t);
+        int k = s1 - 1 - s0;
+        hipLaunchKernelGGL(k_rev_stage2<T>, dim3(gn), dim3(kAB), 0, s, an, s1 - 1, set_step,
+                           stack(k), rp0(k), rb(k), stack(k + 1), L1, LT, LP0, u, v, gx, gy,
+                           c->cat, coef(), ign(), D, acc);
+        for (int n_ = s1 - 1; n_ >= s0; n_--) {
+            k = n_ - s0;
+            an.t = A->tstep[n_];
+            an.ign_active = ign_active_at(an.t);
+            hipLaunchKernelGGL(k_rev_stage1<T>, dim3(gn), dim3(kAB), 0, s, an, D, rb(k), L1, LB,
+                               rp0(k), u, v, gx, gy, c->cat, coef(), D1, gu, gv, gm);
+            if (n_ > s0) {
+                AdjArgs ap = a;
+                ap.t = A->tstep[n_ - 1];
+                ap.ign_active = ign_active_at(ap.t);
+                hipLaunchKernelGGL(k_rev_psi_stage2<T>, dim3(gn), dim3(kAB), 0, s, an, ap,
+                                   n_ - 1, D1, rp0(k), LP0, LB, stack(k), set_step, stack(k - 1),
+                                   rp0(k - 1), rb(k - 1), L1, LT, u, v, gx, gy, c->cat, coef(),
+                                   ign(), D, acc);
+            } else {
+                hipLaunchKernelGGL(k_rev_psi<T>, dim3(gn), dim3(kAB), 0, s, an, D1, rp0(k), LP0,
+                                   LB, stack(k), ign(), L1, acc);
+            }
+        }
         return hipGetLastError();
     }
 
@@ -836,7 +958,7 @@ template <typename T> struct Run {
             const int s0 = seg * A->every;
             const int s1 = s0 + A->every < A->nsteps ? s0 + A->every : A->nsteps;
             h = replay(seg);
-            for (int k = s1 - 1; k >= s0 && h == hipSuccess; k--) h = reverse_step(k, k - s0);
+            if (h == hipSuccess) h = reverse_segment(s0, s1);
         }
         if (h != hipSuccess) return FIRE_ERR_HIP;
         // outputs
@@ -847,9 +969,9 @@ template <typename T> struct Run {
         double *part = at<double>(A->L.part), *small = at<double>(A->L.small);
         hipLaunchKernelGGL(k_cat_partial, dim3(gn), dim3(kAB), 0, s, at<double>(A->L.gm), c->cat,
                            (int)n, c->ncat, part);
-        hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, s, part, gn, c->ncat, small);
-        hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(64), 0, s, at<double>(A->L.acc), gn, kShift,
-                           small + 256);
+        hipLaunchKernelGGL(k_col_sum, dim3(c->ncat), dim3(kAB), 0, s, part, gn, c->ncat, small);
+        hipLaunchKernelGGL(k_col_sum, dim3(kShift), dim3(kAB), 0, s, at<double>(A->L.acc), gn,
+                           kShift, small + 256);
         h = hipGetLastError();
         if (h == hipSuccess)
             h = hipMemcpyAsync(grad_mult, small, sizeof(double) * c->ncat, hipMemcpyDeviceToHost,

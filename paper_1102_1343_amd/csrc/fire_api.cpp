@@ -118,7 +118,7 @@ namespace fire {
 // arena for fire_step, replay buffers for the adjoint).
 hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
                     const void *u, const void *v, double t, double dt, void *flux_sens,
-                    void *flux_lat, int *status) {
+                    void *flux_lat, int *status, void *rec_p0, void *rec_b) {
     const fire_mesh &m = c->mesh;
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -166,6 +166,8 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     b.ens_doms = nullptr;
     b.ens_tile_dom = nullptr;
     b.ens_clock = nullptr;
+    b.rec_p0 = rec_p0;
+    b.rec_b = rec_b;
 
     return launch_step(m.dtype, a, b, c->stream);
 }

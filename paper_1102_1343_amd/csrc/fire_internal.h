@@ -78,6 +78,7 @@ struct StepBuffers {
     const EnsDomain *ens_doms;          // non-null for an ensemble launch; then
     const int32_t *ens_tile_dom;        // psi_in / psi_out are the two buffers and
     const EnsClock *ens_clock;          // the clock says which is current
+    void *rec_p0, *rec_b;               // non-null: also write psi' and psi* (one domain)
 };
 
 }  // namespace fire
@@ -128,6 +129,6 @@ void default_tile(const fire_mesh *m, int *tx, int *ty);
 bool tile_ok(const fire_mesh *m, int tile_x, int tile_y);
 hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
                     const void *u, const void *v, double t, double dt, void *flux_sens,
-                    void *flux_lat, int *status);
+                    void *flux_lat, int *status, void *rec_p0 = nullptr, void *rec_b = nullptr);
 
 }  // namespace fire

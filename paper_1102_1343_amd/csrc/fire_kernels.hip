@@ -115,13 +115,13 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 // The fused step.  KR = frame rows per thread (frame height <= 4 KR).
 // LDS frames: A holds psi^n, then psi^{n+1}, then the latent flux; B holds
 // psi*, then the sensible flux; C holds the node ignition times t^.
-template <typename T, int KR, bool SMALL>
+template <typename T, int KR, bool SMALL, bool REC>
 __device__ __forceinline__ void
 step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double tnow,
           const fire_ignition *ign, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
           const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
           const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
-          T *__restrict__ fsens, T *__restrict__ flat, int *status) {
+          T *__restrict__ fsens, T *__restrict__ flat, int *status, T *rec_p0, T *rec_b) {
     constexpr int FHM = kNR * KR;
     __shared__ T A[FHM][kFW];
     __shared__ T B[FHM][kFW];
@@ -272,6 +272,10 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
             C[fy][tx] = pn >= T(0) ? tp : ti;
             if (xr3 && fy >= 3 && fy < a.tile_y + 3) {
                 at<SMALL>(psi_out, idx) = pn;
+                if (REC) {   // psi' and psi* of the step, for the reverse pass
+                    at<SMALL>(rec_p0, idx) = pn0;
+                    at<SMALL>(rec_b, idx) = B[fy][tx];
+                }
                 if (!(ti == told)) at<SMALL>(tign, idx) = ti;
                 const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
                 if (edge && pn < T(0)) st |= kStBoundary;
@@ -380,18 +384,20 @@ template <typename T, int KR> constexpr int waves_per_simd() {
     return (sizeof(T) == 4 && KR == 7) ? 6 : 1;
 }
 
-template <typename T, int KR, bool SMALL>
+// REC: also write psi' (after ignition) and psi* (Heun stage 1) of every
+// node, which the reverse pass of a differentiable run reads.
+template <typename T, int KR, bool SMALL, bool REC>
 __global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
 k_step(const StepArgs a, const fire_ignition *ign, const T *__restrict__ psi_in,
        T *__restrict__ psi_out, T *tign, T *frac, const T *__restrict__ uw,
        const T *__restrict__ vw, const T *__restrict__ dzdx, const T *__restrict__ dzdy,
        const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
-       T *__restrict__ flat, int *status) {
+       T *__restrict__ flat, int *status, T *__restrict__ rec_p0, T *__restrict__ rec_b) {
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
     if (tile >= a.ntiles) return;
-    step_tile<T, KR, SMALL>(a, tile, 0u, a.t, ign, psi_in, psi_out, tign, frac, uw, vw, dzdx,
-                            dzdy, cat, coef, fsens, flat, status);
+    step_tile<T, KR, SMALL, REC>(a, tile, 0u, a.t, ign, psi_in, psi_out, tign, frac, uw, vw,
+                                 dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b);
 }
 
 // An ensemble of domains in one launch: the tiles of all domains form one
@@ -437,14 +443,15 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
     if (SMALL) {
         // the member's first element goes into the 32-bit element index, so
         // the array bases stay the launch's (no per-member 64-bit pointers)
-        step_tile<T, KR, SMALL>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, ign, pin, pout,
-                                tign, frac, uw, vw, dzdx, dzdy, cat, coef, fsens + a0,
-                                flat + a0, status + di);
+        step_tile<T, KR, SMALL, false>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, ign, pin,
+                                       pout, tign, frac, uw, vw, dzdx, dzdy, cat, coef,
+                                       fsens + a0, flat + a0, status + di, nullptr, nullptr);
     } else {
         const size_t c0 = (size_t)d.cell_off;
-        step_tile<T, KR, SMALL>(a, g - d.tile0, 0u, tnow, ign, pin + c0, pout + c0, tign + c0,
-                                frac + c0, uw + c0, vw + c0, dzdx + c0, dzdy + c0, cat + c0,
-                                coef, fsens + a0, flat + a0, status + di);
+        step_tile<T, KR, SMALL, false>(a, g - d.tile0, 0u, tnow, ign, pin + c0, pout + c0,
+                                       tign + c0, frac + c0, uw + c0, vw + c0, dzdx + c0,
+                                       dzdy + c0, cat + c0, coef, fsens + a0, flat + a0,
+                                       status + di, nullptr, nullptr);
     }
 }
 
@@ -553,11 +560,18 @@ hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
                            (T *)b.psi_out, (T *)b.tign, (T *)b.frac, (const T *)b.u,
                            (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy, b.cat,
                            (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
-    } else {
-        hipLaunchKernelGGL((k_step<T, KR, SMALL>), dim3(grid), dim3(kFW, kNR), dyn, s, a, b.ign,
-                           (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
+    } else if (b.rec_p0) {
+        hipLaunchKernelGGL((k_step<T, KR, SMALL, true>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+                           b.ign, (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
                            (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
-                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
+                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
+                           (T *)b.rec_p0, (T *)b.rec_b);
+    } else {
+        hipLaunchKernelGGL((k_step<T, KR, SMALL, false>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
+                           b.ign, (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
+                           (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
+                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
+                           (T *)nullptr, (T *)nullptr);
     }
     return hipGetLastError();
 }

@@ -124,7 +124,7 @@ def test_autograd_wrapper_matches_abi(case64):
     assert np.array_equal(host(v.grad), gv)
     assert np.array_equal(m.grad.numpy(), gm)
     assert np.array_equal(s.grad.numpy(), gs)
-    assert abs(float(L) - case.L()) <= 1e-9 * abs(case.L())
+    assert abs(float(L.detach()) - case.L()) <= 1e-9 * abs(case.L())
 
 
 def test_backward_after_more_steps_is_refused(case64):

@@ -50,6 +50,8 @@ def workload(name):
         return synth.uniform_fire(128), "f64"
     if name == "adjoint1024":
         return synth.adjoint_case(n=1024, steps=500, field_dtype=np.float32), "f32"
+    if name == "wind8192":
+        return synth.atmosphere(820, 820, nz=40, dx=60.0, dy=60.0, dtype=np.float32), "f32"
     if name == "ensemble256":
         return synth.ensemble(ndom=256, side_min=256, side_max=1024, steps=500,
                               field_dtype=np.float32), "f32"
@@ -124,7 +126,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="patchy8192",
                     choices=("patchy8192", "patchy2048", "uniform128", "ensemble256",
-                             "adjoint1024"))
+                             "adjoint1024", "wind8192"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
@@ -168,6 +170,8 @@ def main():
     log(f"generated in {time.perf_counter() - t:.1f} s")
     if args.workload == "adjoint1024":
         return run_adjoint(args, *prob, dtype)
+    if args.workload == "wind8192":
+        return run_wind(args, prob, dtype)
     if args.steps is None:
         args.steps = min(1000, (prob[0] if isinstance(prob, list) else prob).steps)
     if args.workload == "ensemble256":
@@ -392,6 +396,97 @@ def run_adjoint(args, prob, pert, dtype):
                                    "shift": float(np.linalg.norm(gs))}},
         "roofline": None,
         "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_wind(args, atm, dtype):
+    """Coupling input: the staggered atmosphere wind (820 x 820 columns of
+    60 m, 40 levels) to the 8192 x 8192 fire mesh at 6.1 m, K calls."""
+    import numpy as np
+    import torch
+    import oracle.wind as W
+    from paper_1102_1343_amd import fire as F
+
+    nx = ny = 8192
+    sr = 10
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).to("cuda", tdt) for k, v in atm.items()}
+    nz, nay, nax1 = dev["u3"].shape
+    nax = nax1 - 1
+    nb = F.wind_scratch_bytes(nax, nay, nz, nx, ny, sr, sr, tdt)
+    scratch = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    u = torch.empty((ny, nx), dtype=tdt, device="cuda")
+    v = torch.empty_like(u)
+    stream = torch.cuda.current_stream()
+    inputs = [dev[k] for k in ("u3", "v3", "phi", "hgt", "z0")]
+
+    def call():
+        F.wind_interp(*inputs, nx, ny, sr, sr, out=(u, v), scratch=scratch)
+
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    K = args.steps or 200
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(K):
+        ev[k][0].record(stream)
+        call()
+        ev[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    avg_s = sum(a.elapsed_time(b) for a, b in ev) / K / 1e3
+    value = nx * ny * K / (total_ms / 1e3)
+    es = 4 if dtype == "f32" else 8
+    alg = 2 * es * nx * ny            # the two outputs; the staggered inputs are ~1 % of it
+    log(f"{K} calls in {total_ms:.2f} ms, avg {avg_s * 1e6:.1f} us per call")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (cpu_baseline)")
+        sub = {k: np.asarray(atm[k], dtype=np.float64) for k in atm}
+        w = 40                          # 40 x 40 columns -> 400 x 400 fire cells
+        win = dict(u3=sub["u3"][:, :w, :w + 1], v3=sub["v3"][:, :w + 1, :w],
+                   phi=sub["phi"][:, :w, :w], hgt=sub["hgt"][:w, :w], z0=sub["z0"][:w, :w])
+        n = 0
+        t = time.perf_counter()
+        while time.perf_counter() - t < args.cpu_seconds or n == 0:
+            W.fire_wind(win["u3"], win["v3"], win["phi"], win["hgt"], win["z0"], w * sr, w * sr,
+                        sr, sr)
+            n += 1
+        el = time.perf_counter() - t
+        cpu = {"value": (w * sr) ** 2 * n / el, "unit": "fire cells/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"FP64 oracle (numpy, one thread), the {w}x{w}-column corner of the "
+                         f"atmosphere to its {w * sr}x{w * sr} fire cells, {n} times, {el:.1f} s"}
+        log(f"oracle {cpu['value']:.3e} fire cells/s")
+    out = {
+        "metric": "surface wind fire cells/s",
+        "value": value,
+        "unit": "fire cells/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"wind8192: {nax}x{nay} atmosphere columns of 60 m, {nz} levels, "
+                               f"staggered u/v -> {nx}x{ny} fire mesh (6 m) at 6.1 m",
+                   "nax": nax, "nay": nay, "nz": nz, "nx": nx, "ny": ny},
+        "roofline": {"bound": "hbm", "achieved": round(alg / avg_s / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_wind_vertical + k_wind_bilinear",
+                     "avg_kernel_us": round(avg_s * 1e6, 2),
+                     "alg_bytes_per_fire_cell": 2 * es},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0

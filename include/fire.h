@@ -326,6 +326,49 @@ int fire_adj_backward(fire_adj *a, const void *dF, void *grad_u, void *grad_v,
 /* Releases the handle (host memory only). */
 void fire_adj_destroy(fire_adj *a);
 
+/* ------------------------------------------------------------------------
+ * Coupling input (Sect. 6): the atmosphere's staggered horizontal wind to
+ * the fire cell centres.  The atmosphere mesh has nax x nay cells of
+ * (sr_x dx) x (sr_y dy) covering the fire mesh from the same corner, and nz
+ * cells in the vertical.  u lives on the x-faces (nax + 1 per row), v on
+ * the y-faces (nay + 1 per column), Fig. 1.  For each face point the wind at
+ * height zf above the terrain is the piecewise-linear interpolant in ln z
+ * through (ln z0, 0) and the level values at the heights of the cell
+ * centres, z_k = (phi_k + phi_{k+1}) / (2 g) - hgt, taken from the two
+ * columns sharing the face (averaged; the one column at the domain edge);
+ * levels at or below z0 are left out, the top value is kept above the
+ * highest level, and zf <= z0 gives 0.  Each component is then
+ * interpolated bilinearly to the fire cell centres, coordinates clamped to
+ * the extent of its face points.  The result is the (u, v) fire_step takes.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t nax, nay, nz;     /* atmosphere cells in x and y; vertical cells  */
+    int32_t sr_x, sr_y;       /* fire cells per atmosphere cell              */
+    int32_t nx, ny;           /* fire mesh, nx <= nax sr_x, ny <= nay sr_y,
+                                 both < 2^24, nx ny <= 2^31                   */
+    int32_t dtype;            /* fire_dtype of every array                   */
+    double zf;                /* height of the fire wind above terrain (m), 6.1 */
+    double g;                 /* gravitational acceleration (m/s^2), 9.81    */
+} fire_wind_grid;
+
+/* Bytes of device scratch fire_wind_interp needs (0 if the grid is invalid). */
+size_t fire_wind_scratch_bytes(const fire_wind_grid *grid);
+
+/*
+ * Device arrays, row-major with x fastest:
+ *   u3  [nz][nay][nax+1]   u on the x-faces (m/s)
+ *   v3  [nz][nay+1][nax]   v on the y-faces (m/s)
+ *   phi [nz+1][nay][nax]   geopotential at the cell bottoms/tops (m^2/s^2)
+ *   hgt [nay][nax]         terrain height (m)
+ *   z0  [nay][nax]         roughness height (m)
+ *   u, v [ny][nx]          output, wind at zf on the fire cell centres
+ * scratch: device, fire_wind_scratch_bytes(), 256-byte aligned.
+ * Asynchronous on stream.
+ */
+int fire_wind_interp(const fire_wind_grid *grid, const void *u3, const void *v3,
+                     const void *phi, const void *hgt, const void *z0, void *u, void *v,
+                     void *scratch, size_t scratch_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

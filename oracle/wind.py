@@ -51,6 +51,22 @@ def log_interp(z, val, z0, zf):
     return float(np.interp(math.log(zf), xs, ys))
 
 
+def u_point(u3, zc, z0, I, J, zf):
+    """u at height zf under u-point (I, J) (W2, W3); zc from cell_heights."""
+    nax = zc.shape[2]
+    cl, cr = max(I - 1, 0), min(I, nax - 1)
+    z = 0.5 * (zc[:, J, cl] + zc[:, J, cr])
+    return log_interp(z, u3[:, J, I], 0.5 * (z0[J, cl] + z0[J, cr]), zf)
+
+
+def v_point(v3, zc, z0, I, J, zf):
+    """v at height zf under v-point (I, J)."""
+    nay = zc.shape[1]
+    cb, ct = max(J - 1, 0), min(J, nay - 1)
+    z = 0.5 * (zc[:, cb, I] + zc[:, ct, I])
+    return log_interp(z, v3[:, J, I], 0.5 * (z0[cb, I] + z0[ct, I]), zf)
+
+
 def staggered_surface_wind(u3, v3, phi, hgt, z0, zf, g=G):
     """u at the u-points [nay][nax+1] and v at the v-points [nay+1][nax] at
     height zf (W1-W3)."""
@@ -63,29 +79,30 @@ def staggered_surface_wind(u3, v3, phi, hgt, z0, zf, g=G):
     vf = np.zeros((nay + 1, nax))
     for J in range(nay):
         for I in range(nax + 1):
-            cl, cr = max(I - 1, 0), min(I, nax - 1)
-            z = 0.5 * (zc[:, J, cl] + zc[:, J, cr])
-            uf[J, I] = log_interp(z, u3[:, J, I], 0.5 * (z0[J, cl] + z0[J, cr]), zf)
+            uf[J, I] = u_point(u3, zc, z0, I, J, zf)
     for J in range(nay + 1):
         for I in range(nax):
-            cb, ct = max(J - 1, 0), min(J, nay - 1)
-            z = 0.5 * (zc[:, cb, I] + zc[:, ct, I])
-            vf[J, I] = log_interp(z, v3[:, J, I], 0.5 * (z0[cb, I] + z0[ct, I]), zf)
+            vf[J, I] = v_point(v3, zc, z0, I, J, zf)
     return uf, vf
 
 
 def bilinear(f, px, py):
     """Bilinear value of the 2-D point field f[J][I] (I along x) at the
     fractional point coordinates (px, py), each clamped to the field (W4)."""
-    ny, nx = f.shape
+    f = np.asarray(f)
+    return bilinear_fn(lambda J, I: f[J, I], f.shape[1], f.shape[0], px, py)
+
+
+def bilinear_fn(get, nx, ny, px, py):
+    """bilinear() on a field of nx x ny points given by get(J, I)."""
     px = min(max(px, 0.0), nx - 1.0)
     py = min(max(py, 0.0), ny - 1.0)
     i0 = min(int(math.floor(px)), max(nx - 2, 0))
     j0 = min(int(math.floor(py)), max(ny - 2, 0))
     i1, j1 = min(i0 + 1, nx - 1), min(j0 + 1, ny - 1)
     tx, ty = px - i0, py - j0
-    return ((1 - tx) * (1 - ty) * f[j0, i0] + tx * (1 - ty) * f[j0, i1]
-            + (1 - tx) * ty * f[j1, i0] + tx * ty * f[j1, i1])
+    return ((1 - tx) * (1 - ty) * get(j0, i0) + tx * (1 - ty) * get(j0, i1)
+            + (1 - tx) * ty * get(j1, i0) + tx * ty * get(j1, i1))
 
 
 def fire_wind_at(uf, vf, i, j, sr_x, sr_y):
@@ -96,6 +113,38 @@ def fire_wind_at(uf, vf, i, j, sr_x, sr_y):
     X = (i + 0.5) / sr_x
     Y = (j + 0.5) / sr_y
     return bilinear(uf, X, Y - 0.5), bilinear(vf, X - 0.5, Y)
+
+
+def fire_wind_sample(u3, v3, phi, hgt, z0, i, j, sr_x, sr_y, zf=6.1, g=G):
+    """(u, v) at fire cell (i, j), evaluating only the staggered points it
+    needs (for sampled checks on large meshes)."""
+    u3 = np.asarray(u3)
+    v3 = np.asarray(v3)
+    z0 = np.asarray(z0, dtype=np.float64)
+    phi = np.asarray(phi)
+    hgt = np.asarray(hgt)
+    nay, nax = hgt.shape
+    cols = {}
+
+    def zc_col(J, I):
+        if (J, I) not in cols:
+            cols[(J, I)] = (0.5 * (phi[:-1, J, I].astype(np.float64)
+                                   + phi[1:, J, I].astype(np.float64)) / g - float(hgt[J, I]))
+        return cols[(J, I)]
+
+    class ZC:   # zc[:, J, I] on demand
+        shape = (phi.shape[0] - 1, nay, nax)
+
+        def __getitem__(self, key):
+            _, J, I = key
+            return zc_col(J, I)
+
+    zc = ZC()
+    X = (i + 0.5) / sr_x
+    Y = (j + 0.5) / sr_y
+    u = bilinear_fn(lambda J, I: u_point(u3, zc, z0, I, J, zf), nax + 1, nay, X, Y - 0.5)
+    v = bilinear_fn(lambda J, I: v_point(v3, zc, z0, I, J, zf), nax, nay + 1, X - 0.5, Y)
+    return u, v
 
 
 def fire_wind(u3, v3, phi, hgt, z0, nx, ny, sr_x, sr_y, zf=6.1, g=G):

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfire_gfx950.so")
-SOURCES = ["fire_kernels.hip", "fire_api.cpp", "fire_ens.cpp", "fire_adj.hip"]
+SOURCES = ["fire_kernels.hip", "fire_api.cpp", "fire_ens.cpp", "fire_adj.hip",
+           "fire_wind.hip"]
 
 # packed FP32 instructions are kept out of the generated code on purpose
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

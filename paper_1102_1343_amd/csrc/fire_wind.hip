@@ -1,0 +1,252 @@
+// Coupling input of the fire step (Sect. 6): the atmosphere's staggered
+// horizontal wind brought to the centres of the fire cells.
+//
+// 1. k_wind_vertical, one thread per staggered point (u-points at the
+//    x-faces, v-points at the y-faces of the atmospheric cells, Fig. 1):
+//    heights of the cell centres above the terrain from the geopotential,
+//    z_k = (phi_k + phi_{k+1}) / 2g - h, averaged over the two columns that
+//    share the face (the one column at the domain edge), and the value at
+//    z_f from the piecewise-linear interpolant in ln z through (ln z0, 0)
+//    and the level values above z0 (0 if z_f <= z0, the top value above the
+//    highest level).  Computed in double.
+// 2. k_wind_bilinear, one thread per fire cell: bilinear interpolation of
+//    each component from its staggered points, coordinates clamped to the
+//    points' extent, in the array precision.  The kernel writes 2 values per
+//    fire cell and reads a field ~sr_x sr_y times smaller (from cache), so it
+//    is bound by the HBM writes.
+#include <cmath>
+
+#include "fire_internal.h"
+
+namespace fire {
+namespace {
+
+constexpr int kWB = 256;
+
+struct WindArgs {
+    int32_t nax, nay, nz, sr_x, sr_y, nx, ny;
+    int32_t vec;       // rows of 4k cells and 4-element-aligned outputs: vector stores
+    double zf, g;
+    double rsx, rsy;   // 1 / sr_x, 1 / sr_y
+};
+
+template <typename T>
+__device__ __forceinline__ double cell_z(const T *phi, const T *hgt, int ncol, int k, int c,
+                                         double g) {
+    return 0.5 * ((double)phi[(size_t)k * ncol + c] + (double)phi[(size_t)(k + 1) * ncol + c]) / g -
+           (double)hgt[c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWB)
+k_wind_vertical(const WindArgs a, const T *u3, const T *v3, const T *phi, const T *hgt,
+                const T *z0, T *uf, T *vf) {
+    const int nu = (a.nax + 1) * a.nay, nv = a.nax * (a.nay + 1);
+    const int idx = blockIdx.x * kWB + threadIdx.x;
+    if (idx >= nu + nv) return;
+    const int ncol = a.nax * a.nay;
+    int ca, cb, np, pi;
+    const T *val;
+    if (idx < nu) {   // u-point (I, J) on the x-face between columns I-1 and I
+        const int J = idx / (a.nax + 1), I = idx - J * (a.nax + 1);
+        ca = J * a.nax + (I > 0 ? I - 1 : 0);
+        cb = J * a.nax + (I < a.nax ? I : a.nax - 1);
+        val = u3;
+        np = nu;
+        pi = idx;
+    } else {          // v-point (I, J) on the y-face between rows J-1 and J
+        const int q = idx - nu;
+        const int J = q / a.nax, I = q - J * a.nax;
+        ca = (J > 0 ? J - 1 : 0) * a.nax + I;
+        cb = (J < a.nay ? J : a.nay - 1) * a.nax + I;
+        val = v3;
+        np = nv;
+        pi = q;
+    }
+    const double zr = 0.5 * ((double)z0[ca] + (double)z0[cb]);
+    double r = 0.0;
+    if (a.zf > zr) {
+        const double lzf = ::log(a.zf);
+        double lz_prev = ::log(zr), v_prev = 0.0;
+        bool done = false;
+        for (int k = 0; k < a.nz && !done; k++) {
+            const double zk = 0.5 * (cell_z(phi, hgt, ncol, k, ca, a.g) +
+                                     cell_z(phi, hgt, ncol, k, cb, a.g));
+            if (!(zk > zr)) continue;
+            const double vk = (double)val[(size_t)k * np + pi];
+            const double lzk = ::log(zk);
+            if (lzf <= lzk) {
+                r = v_prev + (lzf - lz_prev) * ((vk - v_prev) / (lzk - lz_prev));
+                done = true;
+            } else {
+                lz_prev = lzk;
+                v_prev = vk;
+            }
+        }
+        if (!done) r = v_prev;
+    }
+    if (idx < nu) uf[pi] = T(r);
+    else vf[pi] = T(r);
+}
+
+// Interpolation position along one axis of a point field of n points at
+// coordinate p = N / Dn (an exact rational: fire centres and face points sit
+// at multiples of 1/(2 sr) in atmosphere-cell units), clamped to [0, n - 1]:
+// lower point k0, upper k1, weight t (exact up to one rounding of rem/Dn).
+template <typename T> struct Axis {
+    int k0, k1;
+    T t;
+};
+
+template <typename T> __device__ __forceinline__ Axis<T> axis(int N, int Dn, T rDn, int n) {
+    Axis<T> r;
+    if (n == 1) {
+        r.k0 = r.k1 = 0;
+        r.t = T(0);
+    } else if (N <= 0) {
+        r.k0 = 0;
+        r.k1 = 1;
+        r.t = T(0);
+    } else if (N >= (n - 1) * Dn) {
+        r.k0 = n - 2;
+        r.k1 = n - 1;
+        r.t = T(1);
+    } else {
+        // N / Dn from the reciprocal, then corrected to the exact quotient
+        int k = (int)((float)N * (float)rDn);
+        int rem = N - k * Dn;
+        if (rem < 0) {
+            k--;
+            rem += Dn;
+        } else if (rem >= Dn) {
+            k++;
+            rem -= Dn;
+        }
+        r.k0 = k;
+        r.k1 = k + 1;
+        r.t = T(rem) * rDn;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T bilin(const T *f, int fnx, const Axis<T> &x, const Axis<T> &y) {
+    const T *r0 = f + (size_t)y.k0 * fnx, *r1 = f + (size_t)y.k1 * fnx;
+    return (T(1) - x.t) * (T(1) - y.t) * r0[x.k0] + x.t * (T(1) - y.t) * r0[x.k1] +
+           (T(1) - x.t) * y.t * r1[x.k0] + x.t * y.t * r1[x.k1];
+}
+
+// One fire row per work-group (the y weights are the same along it); each
+// thread makes 4 consecutive cells and, when rows are 4-aligned, stores them
+// as one 16-byte vector.  A fire centre is at x/DX = (i + 1/2)/sr_x;
+// u-points at (I, J + 1/2), v-points at (I + 1/2, J) in atmosphere-cell
+// units.  Arithmetic in the array precision.
+template <typename T> struct alignas(4 * sizeof(T)) W4 { T a, b, c, d; };
+
+template <typename T>
+__global__ void __launch_bounds__(kWB)
+k_wind_bilinear(const WindArgs a, const T *uf, const T *vf, T *u, T *v) {
+    const int j = blockIdx.x;
+    const int Dx = 2 * a.sr_x, Dy = 2 * a.sr_y;
+    const T rx = T(a.rsx) * T(0.5), ry = T(a.rsy) * T(0.5);
+    // x/DX = (2i + 1) / (2 sr_x), shifted by -1/2 (= -sr_x / (2 sr_x)) for v
+    const Axis<T> uy = axis(2 * j + 1 - a.sr_y, Dy, ry, a.nay);
+    const Axis<T> vy = axis(2 * j + 1, Dy, ry, a.nay + 1);
+    const size_t row = (size_t)j * a.nx;
+    const bool vec = a.vec != 0;
+    for (int i0 = 4 * threadIdx.x; i0 < a.nx; i0 += 4 * kWB) {
+        T ou[4], ov[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int i = i0 + q < a.nx ? i0 + q : a.nx - 1;
+            const Axis<T> ux = axis(2 * i + 1, Dx, rx, a.nax + 1);
+            const Axis<T> vx = axis(2 * i + 1 - a.sr_x, Dx, rx, a.nax);
+            ou[q] = bilin(uf, a.nax + 1, ux, uy);
+            ov[q] = bilin(vf, a.nax, vx, vy);
+        }
+        if (vec) {
+            *reinterpret_cast<W4<T> *>(u + row + i0) = W4<T>{ou[0], ou[1], ou[2], ou[3]};
+            *reinterpret_cast<W4<T> *>(v + row + i0) = W4<T>{ov[0], ov[1], ov[2], ov[3]};
+        } else {
+            for (int q = 0; q < 4 && i0 + q < a.nx; q++) {
+                u[row + i0 + q] = ou[q];
+                v[row + i0 + q] = ov[q];
+            }
+        }
+    }
+}
+
+bool grid_ok(const fire_wind_grid *g) {
+    if (!g) return false;
+    if (g->nax < 1 || g->nay < 1 || g->nz < 1 || g->sr_x < 1 || g->sr_y < 1) return false;
+    if (g->nx < 1 || g->ny < 1 || g->nx > (int64_t)g->nax * g->sr_x ||
+        g->ny > (int64_t)g->nay * g->sr_y)
+        return false;
+    if ((int64_t)g->nx * g->ny > ((int64_t)1 << 31)) return false;
+    if (g->nx >= (1 << 24) || g->ny >= (1 << 24)) return false;   // axis positions in int/float
+    if ((int64_t)(g->nax + 1) * (g->nay + 1) * 2 > ((int64_t)1 << 31)) return false;
+    if (!(g->zf > 0.0) || !std::isfinite(g->zf) || !(g->g > 0.0) || !std::isfinite(g->g))
+        return false;
+    return g->dtype == FIRE_F32 || g->dtype == FIRE_F64;
+}
+
+size_t stag_elems(const fire_wind_grid *g) {
+    return (size_t)(g->nax + 1) * g->nay + (size_t)g->nax * (g->nay + 1);
+}
+
+template <typename T>
+hipError_t run(const fire_wind_grid *g, const void *u3, const void *v3, const void *phi,
+               const void *hgt, const void *z0, void *u, void *v, void *scratch,
+               hipStream_t s) {
+    WindArgs a;
+    a.nax = g->nax;
+    a.nay = g->nay;
+    a.nz = g->nz;
+    a.sr_x = g->sr_x;
+    a.sr_y = g->sr_y;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.vec = (g->nx % 4 == 0) && ((uintptr_t)u % (4 * sizeof(T)) == 0) &&
+            ((uintptr_t)v % (4 * sizeof(T)) == 0);
+    a.zf = g->zf;
+    a.g = g->g;
+    a.rsx = 1.0 / g->sr_x;   // 1/(2 sr) = rs / 2 is exact in binary
+    a.rsy = 1.0 / g->sr_y;
+    T *uf = (T *)scratch;
+    T *vf = uf + (size_t)(g->nax + 1) * g->nay;
+    const int npts = (int)stag_elems(g);
+    hipLaunchKernelGGL(k_wind_vertical<T>, dim3((npts + kWB - 1) / kWB), dim3(kWB), 0, s, a,
+                       (const T *)u3, (const T *)v3, (const T *)phi, (const T *)hgt,
+                       (const T *)z0, uf, vf);
+    hipLaunchKernelGGL(k_wind_bilinear<T>, dim3(g->ny), dim3(kWB), 0, s, a, (const T *)uf,
+                       (const T *)vf, (T *)u, (T *)v);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace fire
+
+using namespace fire;
+
+extern "C" {
+
+size_t fire_wind_scratch_bytes(const fire_wind_grid *g) {
+    if (!grid_ok(g)) return 0;
+    return align_up(stag_elems(g) * (g->dtype == FIRE_F64 ? 8 : 4));
+}
+
+int fire_wind_interp(const fire_wind_grid *g, const void *u3, const void *v3, const void *phi,
+                     const void *hgt, const void *z0, void *u, void *v, void *scratch,
+                     size_t scratch_bytes, void *stream) {
+    if (!grid_ok(g) || !u3 || !v3 || !phi || !hgt || !z0 || !u || !v || !scratch)
+        return FIRE_ERR_ARG;
+    if (scratch_bytes < fire_wind_scratch_bytes(g) || ((uintptr_t)scratch % kAlign) != 0)
+        return FIRE_ERR_ARG;
+    const hipError_t h =
+        g->dtype == FIRE_F64
+            ? run<double>(g, u3, v3, phi, hgt, z0, u, v, scratch, (hipStream_t)stream)
+            : run<float>(g, u3, v3, phi, hgt, z0, u, v, scratch, (hipStream_t)stream);
+    return h == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+}  // extern "C"

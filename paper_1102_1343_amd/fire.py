@@ -54,6 +54,12 @@ class fire_params(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class fire_wind_grid(C.Structure):
+    _fields_ = [("nax", C.c_int32), ("nay", C.c_int32), ("nz", C.c_int32), ("sr_x", C.c_int32),
+                ("sr_y", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("dtype", C.c_int32),
+                ("zf", C.c_double), ("g", C.c_double)]
+
+
 class fire_view(C.Structure):
     _fields_ = [("psi", C.c_void_p), ("tign", C.c_void_p), ("frac", C.c_void_p),
                 ("t", C.c_double)]
@@ -115,6 +121,10 @@ def lib():
         L.fire_adj_backward.argtypes = [vp, vp, vp, vp, P(C.c_double), P(C.c_double)]
         L.fire_adj_destroy.argtypes = [vp]
         L.fire_adj_destroy.restype = None
+        L.fire_wind_scratch_bytes.argtypes = [P(fire_wind_grid)]
+        L.fire_wind_scratch_bytes.restype = C.c_size_t
+        L.fire_wind_interp.argtypes = [P(fire_wind_grid), vp, vp, vp, vp, vp, vp, vp, vp,
+                                       C.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -602,3 +612,56 @@ class FireRun(torch.autograd.Function):
         gu, gv, gm, gs = ctx.adj.backward(gF.detach().to(fire.dtype).contiguous())
         return (gu.to(udt), gv.to(vdt), torch.from_numpy(gm).to(mdev, mdt),
                 torch.from_numpy(np.ascontiguousarray(gs)).to(sdev, sdt), None, None, None, None)
+
+
+def wind_interp(u3, v3, phi, hgt, z0, nx, ny, sr_x, sr_y, zf=6.1, g=9.81, stream=None,
+                out=None, scratch=None):
+    """Surface wind on the fire mesh [ny, nx] from the atmosphere's staggered
+    u3 [nz, nay, nax+1], v3 [nz, nay+1, nax], geopotential phi
+    [nz+1, nay, nax], terrain height and roughness [nay, nax] (device
+    tensors of one floating dtype).  Returns (u, v) device tensors (``out``
+    if given).  With a caller-kept ``scratch`` (uint8 device tensor of at
+    least wind_scratch_bytes() + 256) the call does not wait."""
+    dt = u3.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("float32 or float64 tensors expected")
+    nz, nay, nax1 = u3.shape
+    nax = nax1 - 1
+    shapes = {"v3": (v3, (nz, nay + 1, nax)), "phi": (phi, (nz + 1, nay, nax)),
+              "hgt": (hgt, (nay, nax)), "z0": (z0, (nay, nax))}
+    for name, (t, shp) in shapes.items():
+        if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {shp} {dt}")
+    if not u3.is_contiguous():
+        raise ValueError("u3 must be contiguous")
+    grid = fire_wind_grid(nax, nay, nz, int(sr_x), int(sr_y), int(nx), int(ny),
+                          FIRE_F64 if dt == torch.float64 else FIRE_F32, float(zf), float(g))
+    nb = lib().fire_wind_scratch_bytes(C.byref(grid))
+    if nb == 0:
+        raise FireError(-1, "fire_wind_scratch_bytes")
+    own = scratch is None
+    if own:
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=u3.device)
+    elif scratch.numel() < nb + 256:
+        raise ValueError("scratch too small")
+    base = scratch.data_ptr() + (-scratch.data_ptr()) % 256
+    if out is None:
+        u = torch.empty((int(ny), int(nx)), dtype=dt, device=u3.device)
+        v = torch.empty_like(u)
+    else:
+        u, v = out
+    _check(lib().fire_wind_interp(C.byref(grid), C.c_void_p(u3.data_ptr()),
+                                  C.c_void_p(v3.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                  C.c_void_p(hgt.data_ptr()), C.c_void_p(z0.data_ptr()),
+                                  C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
+                                  C.c_void_p(base), nb, _stream_handle(stream)),
+           "fire_wind_interp")
+    if own:   # the scratch must outlive the asynchronous kernels
+        (stream or torch.cuda.current_stream()).synchronize()
+    return u, v
+
+
+def wind_scratch_bytes(nax, nay, nz, nx, ny, sr_x, sr_y, dtype=torch.float32):
+    grid = fire_wind_grid(nax, nay, nz, sr_x, sr_y, nx, ny,
+                          FIRE_F64 if dtype == torch.float64 else FIRE_F32, 6.1, 9.81)
+    return lib().fire_wind_scratch_bytes(C.byref(grid))

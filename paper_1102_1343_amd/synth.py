@@ -359,3 +359,54 @@ def adjoint_case(n=1024, steps=500, dt=0.25, seed=SEED, field_dtype=np.float64):
     pert = dict(mult=rng.uniform(0.8, 1.2, len(fuels)), wind_scale=1.1,
                 shift=[(2 * dx * math.cos(a), 2 * dx * math.sin(a)) for a in ang])
     return prob, pert
+
+
+def atmosphere(nax, nay, nz=40, dx=60.0, dy=60.0, seed=SEED, dtype=np.float64):
+    """Synthetic lowest atmosphere over nax x nay columns of dx x dy metres:
+    nz stretched levels (cell boundaries 0, 8, 18, 30.5, ... m, ratio 1.25,
+    capped at 500 m spacing) above a terrain of 8 Gaussian hills up to 400 m,
+    geopotential phi = 9.81 (z + h); roughness z0 in [0.03, 0.8] m per column
+    from a smooth random field; u and v on the staggered faces following a
+    log law with a horizontally varying friction velocity (16 Fourier modes,
+    mean 4 m/s at 10 m) and a linear veer of up to 20 degrees over the
+    column.  Returns dict(u3, v3, phi, hgt, z0)."""
+    rng = np.random.default_rng([seed, 9])
+    dz = np.minimum(8.0 * 1.25 ** np.arange(nz), 500.0)
+    zw = np.concatenate([[0.0], np.cumsum(dz)])
+    L = (nax * dx, nay * dy)
+    xc = (np.arange(nax) + 0.5) * dx
+    yc = (np.arange(nay) + 0.5) * dy
+    hgt = np.zeros((nay, nax))
+    for _ in range(8):
+        cx, cy = rng.uniform(0, L[0]), rng.uniform(0, L[1])
+        s = rng.uniform(0.05, 0.2) * max(L)
+        hgt += rng.uniform(50, 400) * np.exp(-(((xc[None] - cx) ** 2) + ((yc[:, None] - cy) ** 2))
+                                             / (2 * s * s))
+    phi = 9.81 * (zw[:, None, None] + hgt[None])
+
+    def smooth(nx_, ny_, x0, y0, amp, base):
+        k = rng.integers(-3, 4, (8, 2))
+        ph = rng.uniform(0, 2 * math.pi, 8)
+        a = rng.normal(0, 1, 8)
+        x = x0 + np.arange(nx_) * dx
+        y = y0 + np.arange(ny_) * dy
+        f = sum(a[m] * np.cos(2 * math.pi * (k[m, 0] * x[None] / L[0] + k[m, 1] * y[:, None] / L[1])
+                              + ph[m]) for m in range(8))
+        return base + amp * f / max(1e-9, np.abs(f).max())
+
+    z0 = np.clip(smooth(nax, nay, 0.5 * dx, 0.5 * dy, 0.35, 0.4), 0.03, 0.8)
+    zc = 0.5 * (zw[:-1] + zw[1:])
+    th = rng.uniform(0, 2 * math.pi)
+    veer = np.radians(20.0) * np.minimum(zc / zc[-1], 1.0)
+
+    def face(nx_, ny_, x0, y0, comp):
+        us = smooth(nx_, ny_, x0, y0, 1.5, 4.0)            # wind at 10 m
+        prof = np.log(np.maximum(zc, 0.05) / 0.1) / math.log(10.0 / 0.1)
+        ang = th + veer
+        c = np.cos(ang) if comp == 0 else np.sin(ang)
+        return (us[None] * (prof * c)[:, None, None]).astype(dtype)
+
+    u3 = face(nax + 1, nay, 0.0, 0.5 * dy, 0)
+    v3 = face(nax, nay + 1, 0.5 * dx, 0.0, 1)
+    c = lambda a: np.ascontiguousarray(a, dtype=dtype)
+    return dict(u3=c(u3), v3=c(v3), phi=c(phi), hgt=c(hgt), z0=c(z0))

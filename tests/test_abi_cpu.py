@@ -128,3 +128,28 @@ def test_adjoint_sizes_and_errors_without_gpu(lib):
     assert lib.fire_adj_init(C.byref(h), None, 10, 5, None, C.c_size_t(0)) == -1
     assert lib.fire_adj_forward(None, None, None, C.c_double(0.25)) == -1
     assert lib.fire_adj_backward(None, None, None, None, None, None) == -1
+
+
+def test_wind_grid_layout_and_errors_without_gpu(lib, tmp_path):
+    from paper_1102_1343_amd import fire as F
+    prog = tmp_path / "wg.c"
+    prog.write_text('#include "fire.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                    'int main(void){printf("%zu %zu %zu\\n", sizeof(fire_wind_grid),'
+                    'offsetof(fire_wind_grid, zf), offsetof(fire_wind_grid, g));return 0;}\n')
+    exe = tmp_path / "wg"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == [C.sizeof(F.fire_wind_grid), F.fire_wind_grid.zf.offset,
+                   F.fire_wind_grid.g.offset]
+    lib.fire_wind_scratch_bytes.restype = C.c_size_t
+    g = F.fire_wind_grid(820, 820, 40, 10, 10, 8192, 8192, F.FIRE_F32, 6.1, 9.81)
+    assert lib.fire_wind_scratch_bytes(C.byref(g)) >= (821 * 820 * 2) * 4
+    for field, val in (("nx", 8201), ("ny", 0), ("nz", 0), ("zf", 0.0), ("g", -1.0),
+                       ("dtype", 5), ("sr_x", 0)):
+        b = F.fire_wind_grid(820, 820, 40, 10, 10, 8192, 8192, F.FIRE_F32, 6.1, 9.81)
+        setattr(b, field, val)
+        assert lib.fire_wind_scratch_bytes(C.byref(b)) == 0, field
+    assert lib.fire_wind_interp(C.byref(g), None, None, None, None, None, None, None, None,
+                                C.c_size_t(0), None) == -1

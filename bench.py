@@ -58,18 +58,19 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("fire_kernels.hip", "fire_internal.h")):
     h = hashlib.sha256()
-    for f in ("fire_kernels.hip", "fire_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1102_1343_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(name, dtype, tile, kernel=KERNEL):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
+def pmc_traffic(name, dtype, tile, kernel=KERNEL,
+                files=("fire_kernels.hip", "fire_internal.h")):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
     counter summary for this workload, if it was taken on the current kernel
-    source with the same tile shape; else None."""
+    source with the same tile shape (None: no tile); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{dtype}_pmc.txt")
     if not os.path.exists(path):
         return None
@@ -77,9 +78,9 @@ def pmc_traffic(name, dtype, tile, kernel=KERNEL):
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     t = re.search(r"tile:\s*(\d+)x(\d+)", txt)
-    if not m or not b or not t or m.group(1) != kernel_source_hash():
+    if not m or not b or m.group(1) != kernel_source_hash(files):
         return None
-    if (int(t.group(1)), int(t.group(2))) != tuple(tile):
+    if tile is not None and (not t or (int(t.group(1)), int(t.group(2))) != tuple(tile)):
         return None
     return float(b.group(1))
 
@@ -482,7 +483,9 @@ def run_wind(args, atm, dtype):
                    "nax": nax, "nay": nay, "nz": nz, "nx": nx, "ny": ny},
         "roofline": {"bound": "hbm", "achieved": round(alg / avg_s / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": pmc_traffic("wind8192", dtype, None, kernel="k_wind",
+                                            files=("fire_wind.hip", "fire_internal.h")),
                      "kernel": "k_wind_vertical + k_wind_bilinear",
                      "avg_kernel_us": round(avg_s * 1e6, 2),
                      "alg_bytes_per_fire_cell": 2 * es},

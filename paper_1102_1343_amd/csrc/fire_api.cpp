@@ -68,6 +68,20 @@ void default_tile(const fire_mesh *m, int *tx, int *ty) {
     *ty = best;
 }
 
+void ignition_window(const fire_ignition *ign, int n, double *lo, double *hi) {
+    *lo = 1.0;
+    *hi = 0.0;
+    for (int g = 0; g < n; g++) {
+        const fire_ignition &q = ign[g];
+        const bool torch = (q.vx != 0.0 || q.vy != 0.0);
+        const double tend = torch ? q.t_end : q.t_start;
+        const double grow = std::isinf(q.ros) ? 0.0 : q.radius / q.ros;
+        const double last = tend + grow;
+        if (g == 0 || q.t_start < *lo) *lo = q.t_start;
+        if (g == 0 || last > *hi) *hi = last;
+    }
+}
+
 bool tile_ok(const fire_mesh *m, int tile_x, int tile_y) {
     const int ymax = m->dtype == FIRE_F64 ? kTileYMax64 : kTileYMax;
     if (tile_x < 1 || tile_x > kTileXMax || tile_x % m->sr_x != 0) return false;
@@ -137,7 +151,9 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     a.ncat = c->ncat;
     a.guard = c->prm.guard_width;
     a.visc_mode = c->prm.viscosity_mode;
-    a.nign = c->nign;
+    double lo, hi;   // no ignition is active outside [lo, hi]: skip the loop
+    ignition_window(c->ign, c->nign, &lo, &hi);
+    a.nign = (t >= lo && t <= hi) ? c->nign : 0;
     a.dx = m.dx;
     a.dy = m.dy;
     a.rdx = 1.0 / m.dx;

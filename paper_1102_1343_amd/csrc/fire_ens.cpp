@@ -17,6 +17,7 @@ struct fire_ens {
     std::vector<fire_mesh> meshes;
     std::vector<int64_t> cell_off, atm_off;   // ndom + 1 entries
     std::vector<int32_t> nign;
+    std::vector<fire_ignition> ign_host;      // FIRE_MAX_IGNITIONS slots per member
     char *arena;
     size_t off_coef, off_fuel, off_ign, off_dom, off_map, off_status, off_t, off_psi[2], off_tign,
         off_frac, total;
@@ -111,6 +112,8 @@ int build_worklist(fire_ens *e) {
         d.rdy = 1.0 / m.dy;
         d.cell_off = e->cell_off[k];
         d.atm_off = e->atm_off[k];
+        ignition_window(e->ign_host.data() + (size_t)k * FIRE_MAX_IGNITIONS, e->nign[k],
+                        &d.t_ign_lo, &d.t_ign_hi);
         const int nt = d.tiles_x * tiles_y;
         for (int i = 0; i < nt; i++) map.push_back(k);
         tile0 += nt;
@@ -187,7 +190,8 @@ int fire_ens_init(fire_ens **out, const fire_mesh *meshes, int32_t ndom, const f
     default_tile(&meshes[0], &e->tile_x, &e->tile_y);
 
     // ignition records padded to FIRE_MAX_IGNITIONS per domain
-    std::vector<fire_ignition> igs((size_t)ndom * FIRE_MAX_IGNITIONS);
+    std::vector<fire_ignition> &igs = e->ign_host;
+    igs.assign((size_t)ndom * FIRE_MAX_IGNITIONS, fire_ignition());
     std::memset(igs.data(), 0, igs.size() * sizeof(fire_ignition));
     for (int k = 0, o = 0; k < ndom; o += nign[k], k++)
         for (int g = 0; g < nign[k]; g++) igs[(size_t)k * FIRE_MAX_IGNITIONS + g] = ign[o + g];

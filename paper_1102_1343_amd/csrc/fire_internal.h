@@ -51,6 +51,7 @@ struct EnsDomain {
     int32_t nax, nay, nign, pad;
     double dx, dy, rdx, rdy;
     int64_t cell_off, atm_off;          // element offsets into the concatenated arrays
+    double t_ign_lo, t_ign_hi;          // ignition_window() of the member's ignitions
 };
 
 // Device-side clock of an ensemble: model time and which psi buffer holds
@@ -127,6 +128,9 @@ bool fuels_ok(const fire_fuel *cats, int ncat);
 bool ignitions_ok(const fire_ignition *ign, int nign);
 void default_tile(const fire_mesh *m, int *tx, int *ty);
 bool tile_ok(const fire_mesh *m, int tile_x, int tile_y);
+// [lo, hi] outside which none of the ignitions is active (the activity test
+// of the step kernel, in the same double arithmetic); lo > hi when n = 0.
+void ignition_window(const fire_ignition *ign, int n, double *lo, double *hi);
 hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
                     const void *u, const void *v, double t, double dt, void *flux_sens,
                     void *flux_lat, int *status, void *rec_p0 = nullptr, void *rec_b = nullptr);

@@ -162,6 +162,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     c.visc_mode = a.visc_mode;
     const T dt = T(a.dt);
     const T hdt = T(0.5 * a.dt);
+    const T rdt = T(1.0 / a.dt);
     const T t = T(tnow);
     const T tp = T(tnow + a.dt);
     const T INF = M<T>::inf();
@@ -311,18 +312,22 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         if (xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi) {
             const uint32_t idx = off0 + fy * unx;
             const T fo = at<SMALL>(frac, idx);
-            const int cv = at<SMALL>(cat, idx);
-            const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
             T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
             mn = vmin(mn, vmin(vmin(A[fy][tx - 1], A[fy][tx]), A[fy][tx + 1]));
             mn = vmin(mn, vmin(vmin(A[fy + 1][tx - 1], A[fy + 1][tx]), A[fy + 1][tx + 1]));
-            T Fn = T(1);
-            if (mn < T(0)) Fn = cell_fraction(A, C, fy, tx, tp, row[kLTf]);
-            const T dF = M<T>::div(fo - Fn, dt);
-            fs = dF * row[kLCh];
-            fl[k] = dF * row[kLCq];
-            if (!(Fn == fo)) at<SMALL>(frac, idx) = Fn;
-            if (!__builtin_isfinite(Fn)) st |= kStNonfinite;
+            // F^{n+1} = F^n = 1 and no flux unless a stencil node burns or F
+            // was already below 1
+            if (mn < T(0) || !(fo == T(1))) {
+                const int cv = at<SMALL>(cat, idx);
+                const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
+                T Fn = T(1);
+                if (mn < T(0)) Fn = cell_fraction(A, C, fy, tx, tp, row[kLTf]);
+                const T dF = (fo - Fn) * rdt;
+                fs = dF * row[kLCh];
+                fl[k] = dF * row[kLCq];
+                if (!(Fn == fo)) at<SMALL>(frac, idx) = Fn;
+                if (!__builtin_isfinite(Fn)) st |= kStNonfinite;
+            }
         }
         if (fy < FH) B[fy][tx] = fs;
     }
@@ -427,7 +432,9 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
     a.tiles_x = d.tiles_x;
     a.nax = d.nax;
     a.nay = d.nay;
-    a.nign = d.nign;
+    // ignitions only inside the window of their activity (none outside)
+    const double tw = clock->t;
+    a.nign = (tw >= d.t_ign_lo && tw <= d.t_ign_hi) ? d.nign : 0;
     a.dx = d.dx;
     a.dy = d.dy;
     a.rdx = d.rdx;

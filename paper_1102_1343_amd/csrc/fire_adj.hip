@@ -55,12 +55,6 @@ __device__ __forceinline__ int ext_idx(const AdjArgs &a, int x, int y) {
     return (y + 1) * (a.nx + 2) + (x + 1);
 }
 
-template <typename T> __device__ __forceinline__ void load_row(const T *coef, int cv, int ncat,
-                                                               T *row) {
-    const int k = cv < ncat - 1 ? cv : ncat - 1;
-    make_row(coef + k * kNCoef, row);
-}
-
 // d ghost(p, q) / d(p, q): ghost = 2p - q when p >= q, else q.
 template <typename T> __device__ __forceinline__ void dghost(T p, T q, T &dp, T &dq) {
     if (p >= q) {
@@ -380,7 +374,7 @@ __device__ __forceinline__ RhsGrad<T> stage_grad(const AdjArgs &a, const T *P, i
     const int i = y * a.nx + x;
     const int cv = cat[i] < a.ncat - 1 ? cat[i] : a.ncat - 1;
     alignas(16) T row[kLRow];
-    make_row(coef + cv * kNCoef, row);
+    make_row(coef + cv * kNCoef, row, T(a.cap));
     return rhs5_grad(P[i], node_g(a, P, x - 1, y), node_g(a, P, x + 1, y), node_g(a, P, x, y - 1),
                      node_g(a, P, x, y + 1), u[i], v[i], gzx[i], gzy[i], row, coef + cv * kNCoef,
                      consts<T>(a));

@@ -51,6 +51,13 @@ __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fm
 __device__ __forceinline__ float vabs(float a) { return __builtin_fabsf(a); }
 __device__ __forceinline__ double vabs(double a) { return __builtin_fabs(a); }
 template <typename T> __device__ __forceinline__ bool is_inf(T a) { return a == M<T>::inf(); }
+// median of three for lo <= hi: min(max(x, lo), hi) in one instruction
+__device__ __forceinline__ float med3(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+__device__ __forceinline__ double med3(double x, double lo, double hi) {
+    return vmin(vmax(x, lo), hi);
+}
 
 // Spread rate, Eq. (3), with the category multiplier and the cap:
 // S = min{cap, m max{S0, R0 + c min{e, max{0,U}}^b + d max{0, tan phi}^2}}.
@@ -80,14 +87,16 @@ enum { kLR0, kLC, kLD, kLB, kLE, kLS0, kLTf, kLCh, kLCq, kLPad0, kLPad1, kLPad2,
 template <typename T> struct alignas(4 * sizeof(T)) V4 { T x, y, z, w; };
 
 // Table row of one category from its coefficient-table entry g.
-template <typename T> __device__ __forceinline__ void make_row(const T *g, T *r) {
+// The floor is stored as min(m S0, cap) so that the floor and the cap of
+// Eq. (3) are one median: min(max(s, m S0), cap) = med3(s, min(m S0, cap), cap).
+template <typename T> __device__ __forceinline__ void make_row(const T *g, T *r, T cap) {
     const T m = g[kM];
     r[kLR0] = m * g[kR0];
     r[kLC] = m * g[kC];
     r[kLD] = m * g[kD];
     r[kLB] = g[kB];
     r[kLE] = g[kE];
-    r[kLS0] = m * g[kS0];
+    r[kLS0] = vmin(m * g[kS0], cap);
     r[kLTf] = T(1) / g[kTf];
     r[kLCh] = g[kCh];
     r[kLCq] = g[kCq];
@@ -98,11 +107,11 @@ template <typename T> __device__ __forceinline__ void make_row(const T *g, T *r)
 template <typename T>
 __device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
     const V4<T> r0 = *reinterpret_cast<const V4<T> *>(row);       // R0 c d b
-    const V4<T> r1 = *reinterpret_cast<const V4<T> *>(row + 4);   // e S0 Tf Ch
-    const T U = vmin(vmax(un, T(0)), r1.x);
+    const V4<T> r1 = *reinterpret_cast<const V4<T> *>(row + 4);   // e min(S0,cap) Tf Ch
+    const T U = med3(un, T(0), r1.x);
     const T g = vmax(tn, T(0));
     const T s = r0.x + r0.y * M<T>::powp(U, r0.w) + r0.z * (g * g);
-    return vmin(vmax(s, r1.y), cap);
+    return med3(s, r1.y, cap);
 }
 
 // Right-hand side of Eq. (12) at a node from its value pc and its four
@@ -118,10 +127,9 @@ __device__ __forceinline__ T rhs5(T pc, T pw, T pe, T ps, T pn, T u, T v, T gzx,
                                   const T *row, const Consts<T> &c) {
     const T dmx = (pc - pw) * c.rdx, dpx = (pe - pc) * c.rdx;
     const T dmy = (pc - ps) * c.rdy, dpy = (pn - pc) * c.rdy;
-    const T ax = vmax(dmx, T(0)), bx = vmin(dpx, T(0));
-    const T ay = vmax(dmy, T(0)), by = vmin(dpy, T(0));
-    const T gx2 = vmax(ax * ax, bx * bx), gy2 = vmax(ay * ay, by * by);
-    const T up = M<T>::sqrt(gx2 + gy2);
+    // max(max(D-,0)^2, min(D+,0)^2) = max(D-, -D+, 0)^2 exactly
+    const T gx = vmax(vmax(dmx, -dpx), T(0)), gy = vmax(vmax(dmy, -dpy), T(0));
+    const T up = M<T>::sqrt(gx * gx + gy * gy);
     const T cx = (pe - pw) * c.rdx, cy = (pn - ps) * c.rdy;
     const T cn2 = cx * cx + cy * cy;
     const T inv = cn2 > T(0) ? M<T>::rsqrt(cn2) : T(0);

@@ -151,8 +151,14 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     // below 2^32 (2^31 for one domain)
     const uint32_t off0 = cbase + (uint32_t)((y0 - kHalo) * nx + gx);
     const uint32_t unx = (uint32_t)nx;
+    // element index of this thread's frame row ty, and the stride between
+    // its rows (row k of the thread is fy = ty + kNR k): idx0 + k rstep, so
+    // the per-row multiply is uniform (scalar) work
+    const uint32_t idx0 = off0 + (uint32_t)ty * unx;
+    const uint32_t rstep = (uint32_t)kNR * unx;
 
-    for (int i = tid; i < a.ncat; i += kBlock) make_row(coef + i * kNCoef, tab + i * kLRow);
+    for (int i = tid; i < a.ncat; i += kBlock)
+        make_row(coef + i * kNCoef, tab + i * kLRow, T(a.ros_cap));
 
     Consts<T> c;
     c.rdx = T(a.rdx);
@@ -166,7 +172,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     const T t = T(tnow);
     const T tp = T(tnow + a.dt);
     const T INF = M<T>::inf();
-    const int ncm1 = a.ncat - 1;
+    const uint32_t ncm1 = (uint32_t)(a.ncat - 1);
 
     // ---- load psi^n on the whole frame and step 1, ignition (Sect. 4.4):
     // psi := min(psi, psi_g); a node lit by this step's ignitions gets the
@@ -177,7 +183,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         const bool in = colin && fy >= ylo && fy < yhi;
-        p0[k] = in ? at<SMALL>(psi_in, off0 + fy * unx) : T(0);
+        p0[k] = in ? at<SMALL>(psi_in, idx0 + (uint32_t)k * rstep) : T(0);
         tig[k] = INF;
     }
     if (a.nign > 0) {
@@ -223,9 +229,9 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         if (xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi) {
-            const uint32_t idx = off0 + fy * unx;
+            const uint32_t idx = idx0 + (uint32_t)k * rstep;
             const int cv = at<SMALL>(cat, idx);
-            const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
+            const T *row = tab + min((uint32_t)cv, ncm1) * (uint32_t)kLRow;
             const T F1 = rhs(A, fy, tx, at<SMALL>(uw, idx), at<SMALL>(vw, idx),
                                at<SMALL>(dzdx, idx), at<SMALL>(dzdy, idx), row, c);
             B[fy][tx] = p0[k] + dt * F1;
@@ -252,9 +258,9 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         const int fy = ty + kNR * k;
         if (xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi) {
             const int gy = y0 - kHalo + fy;
-            const uint32_t idx = off0 + fy * unx;
+            const uint32_t idx = idx0 + (uint32_t)k * rstep;
             const int cv = at<SMALL>(cat, idx);
-            const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
+            const T *row = tab + min((uint32_t)cv, ncm1) * (uint32_t)kLRow;
             const T F2 = rhs(B, fy, tx, at<SMALL>(uw, idx), at<SMALL>(vw, idx),
                                at<SMALL>(dzdx, idx), at<SMALL>(dzdy, idx), row, c);
             const T pn0 = A[fy][tx];
@@ -310,7 +316,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         T fs = T(0);
         fl[k] = T(0);
         if (xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi) {
-            const uint32_t idx = off0 + fy * unx;
+            const uint32_t idx = idx0 + (uint32_t)k * rstep;
             const T fo = at<SMALL>(frac, idx);
             T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
             mn = vmin(mn, vmin(vmin(A[fy][tx - 1], A[fy][tx]), A[fy][tx + 1]));
@@ -319,7 +325,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
             // was already below 1
             if (mn < T(0) || !(fo == T(1))) {
                 const int cv = at<SMALL>(cat, idx);
-                const T *row = tab + (uint32_t)(cv < ncm1 ? cv : ncm1) * (uint32_t)kLRow;
+                const T *row = tab + min((uint32_t)cv, ncm1) * (uint32_t)kLRow;
                 T Fn = T(1);
                 if (mn < T(0)) Fn = cell_fraction(A, C, fy, tx, tp, row[kLTf]);
                 const T dF = (fo - Fn) * rdt;

@@ -45,6 +45,24 @@ template <bool SMALL, typename T> __device__ __forceinline__ T &at(T *p, uint32_
     return p[i];
 }
 
+// Per-cell inputs of the right-hand side: category, wind, terrain gradient.
+template <typename T> struct Inputs {
+    T u, v, gx, gy;
+    int cv;
+};
+
+template <bool SMALL, typename T>
+__device__ __forceinline__ Inputs<T> load_inputs(uint32_t idx, const uint8_t *cat, const T *uw,
+                                                 const T *vw, const T *dzdx, const T *dzdy) {
+    Inputs<T> r;
+    r.cv = at<SMALL>(cat, idx);
+    r.u = at<SMALL>(uw, idx);
+    r.v = at<SMALL>(vw, idx);
+    r.gx = at<SMALL>(dzdx, idx);
+    r.gy = at<SMALL>(dzdy, idx);
+    return r;
+}
+
 // Fill the one-cell ghost ring of frame P around the domain (Sect. 4.1).
 // Ghost nodes read in-domain nodes only, so the ring fills in one pass.
 // Corners (x and y outside) are the x extrapolation of the ghost row.
@@ -225,15 +243,22 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
 
     // ---- step 2a: first Heun stage on the tile plus two rings,
     // psi* = psi^n + dt F(psi^n)
+    // the per-cell inputs of row k + 1 are loaded while row k computes
+    Inputs<T> nxt;
+    auto in1 = [&](int k) {
+        const int fy = ty + kNR * k;
+        return xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi;
+    };
+    if (in1(0)) nxt = load_inputs<SMALL>(idx0, cat, uw, vw, dzdx, dzdy);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        if (xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi) {
-            const uint32_t idx = idx0 + (uint32_t)k * rstep;
-            const int cv = at<SMALL>(cat, idx);
-            const T *row = tab + min((uint32_t)cv, ncm1) * (uint32_t)kLRow;
-            const T F1 = rhs(A, fy, tx, at<SMALL>(uw, idx), at<SMALL>(vw, idx),
-                               at<SMALL>(dzdx, idx), at<SMALL>(dzdy, idx), row, c);
+        const Inputs<T> cur = nxt;
+        if (k + 1 < KR && in1(k + 1))
+            nxt = load_inputs<SMALL>(idx0 + (uint32_t)(k + 1) * rstep, cat, uw, vw, dzdx, dzdy);
+        if (in1(k)) {
+            const T *row = tab + min((uint32_t)cur.cv, ncm1) * (uint32_t)kLRow;
+            const T F1 = rhs(A, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
             B[fy][tx] = p0[k] + dt * F1;
         }
     }
@@ -253,16 +278,22 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     // node times t^ = t' where psi^{n+1} >= 0, else t_i (Eq. 17)
     int st = 0;
     const int gw = a.guard;
+    auto in2 = [&](int k) {
+        const int fy = ty + kNR * k;
+        return xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi;
+    };
+    if (in2(0)) nxt = load_inputs<SMALL>(idx0, cat, uw, vw, dzdx, dzdy);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
-        if (xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi) {
+        const Inputs<T> cur = nxt;
+        if (k + 1 < KR && in2(k + 1))
+            nxt = load_inputs<SMALL>(idx0 + (uint32_t)(k + 1) * rstep, cat, uw, vw, dzdx, dzdy);
+        if (in2(k)) {
             const int gy = y0 - kHalo + fy;
             const uint32_t idx = idx0 + (uint32_t)k * rstep;
-            const int cv = at<SMALL>(cat, idx);
-            const T *row = tab + min((uint32_t)cv, ncm1) * (uint32_t)kLRow;
-            const T F2 = rhs(B, fy, tx, at<SMALL>(uw, idx), at<SMALL>(vw, idx),
-                               at<SMALL>(dzdx, idx), at<SMALL>(dzdy, idx), row, c);
+            const T *row = tab + min((uint32_t)cur.cv, ncm1) * (uint32_t)kLRow;
+            const T F2 = rhs(B, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
             const T pn0 = A[fy][tx];
             const T pn = T(0.5) * (pn0 + B[fy][tx]) + hdt * F2;
             A[fy][tx] = pn;   // stage-1 reads of A ended at the last barrier

@@ -341,14 +341,21 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     // burning sub-cell point: beta = 0 in every sub-cell and F = 1 exactly.
     // The sensible flux goes straight to B (not read in this phase).
     T fl[KR];
+    auto in3 = [&](int k) {
+        const int fy = ty + kNR * k;
+        return xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi;
+    };
+    T fo_next = T(1);   // F of row k + 1 is loaded while row k computes
+    if (in3(0)) fo_next = at<SMALL>(frac, idx0);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         T fs = T(0);
         fl[k] = T(0);
-        if (xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi) {
+        const T fo = fo_next;
+        if (k + 1 < KR && in3(k + 1)) fo_next = at<SMALL>(frac, idx0 + (uint32_t)(k + 1) * rstep);
+        if (in3(k)) {
             const uint32_t idx = idx0 + (uint32_t)k * rstep;
-            const T fo = at<SMALL>(frac, idx);
             T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
             mn = vmin(mn, vmin(vmin(A[fy][tx - 1], A[fy][tx]), A[fy][tx + 1]));
             mn = vmin(mn, vmin(vmin(A[fy + 1][tx - 1], A[fy + 1][tx]), A[fy + 1][tx + 1]));

@@ -72,6 +72,11 @@ def pmc_traffic(name, dtype, tile, kernel=KERNEL,
     counter summary for this workload, if it was taken on the current kernel
     source with the same tile shape (None: no tile); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{dtype}_pmc.txt")
+    if tile is not None:   # one summary per tile shape where several were taken
+        per_tile = os.path.join(ROOT, "profiles",
+                                f"{kernel}_{name}_{dtype}_{tile[0]}x{tile[1]}_pmc.txt")
+        if os.path.exists(per_tile):
+            path = per_tile
     if not os.path.exists(path):
         return None
     txt = open(path).read()

@@ -103,15 +103,31 @@ template <typename T> __device__ __forceinline__ void make_row(const T *g, T *r,
     r[kLPad0] = r[kLPad1] = r[kLPad2] = T(0);
 }
 
-// Spread rate, Eq. (3), with multiplier and cap, from an LDS table row.
+// An object in LDS, addressed with 32-bit offsets.
+template <typename T> using lds_t = T __attribute__((address_space(3)));
+
+// Spread rate, Eq. (3), with multiplier and cap, from a table row (r0, r1:
+// its first eight entries).
 template <typename T>
-__device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
-    const V4<T> r0 = *reinterpret_cast<const V4<T> *>(row);       // R0 c d b
-    const V4<T> r1 = *reinterpret_cast<const V4<T> *>(row + 4);   // e min(S0,cap) Tf Ch
+__device__ __forceinline__ T ros_v4(const V4<T> &r0, const V4<T> &r1, T un, T tn, T cap) {
     const T U = med3(un, T(0), r1.x);
     const T g = vmax(tn, T(0));
     const T s = r0.x + r0.y * M<T>::powp(U, r0.w) + r0.z * (g * g);
     return med3(s, r1.y, cap);
+}
+template <typename T>
+__device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
+    return ros_v4(*reinterpret_cast<const V4<T> *>(row),          // R0 c d b
+                  *reinterpret_cast<const V4<T> *>(row + 4),      // e min(S0,cap) Tf Ch
+                  un, tn, cap);
+}
+template <typename T>
+__device__ __forceinline__ T ros_row(const lds_t<T> *row, T un, T tn, T cap) {
+    const lds_t<V4<T>> *q = reinterpret_cast<const lds_t<V4<T>> *>(row);
+    V4<T> r0, r1;
+    r0.x = q[0].x; r0.y = q[0].y; r0.z = q[0].z; r0.w = q[0].w;
+    r1.x = q[1].x; r1.y = q[1].y; r1.z = q[1].z; r1.w = q[1].w;
+    return ros_v4(r0, r1, un, tn, cap);
 }
 
 // Right-hand side of Eq. (12) at a node from its value pc and its four
@@ -122,9 +138,9 @@ __device__ __forceinline__ T ros_row(const T *row, T un, T tn, T cap) {
 // factor 1/2 cancels in the normal) straight from the two nodes, so it is
 // exactly zero when they are equal -- as at a domain corner whose ghosts
 // mirror the inner nodes -- whatever the compiler fuses.
-template <typename T>
+template <typename T, typename RowPtr>
 __device__ __forceinline__ T rhs5(T pc, T pw, T pe, T ps, T pn, T u, T v, T gzx, T gzy,
-                                  const T *row, const Consts<T> &c) {
+                                  RowPtr row, const Consts<T> &c) {
     const T dmx = (pc - pw) * c.rdx, dpx = (pe - pc) * c.rdx;
     const T dmy = (pc - ps) * c.rdy, dpy = (pn - pc) * c.rdy;
     // max(max(D-,0)^2, min(D+,0)^2) = max(D-, -D+, 0)^2 exactly

@@ -23,9 +23,9 @@ namespace {
 using namespace dev;
 
 // Right-hand side of Eq. (12) at frame cell (fy, fx) of the level set P.
-template <typename T>
+template <typename T, typename RowPtr>
 __device__ __forceinline__ T rhs(const T (*P)[kFW], int fy, int fx, T u, T v, T gzx, T gzy,
-                                 const T *row, const Consts<T> &c) {
+                                 RowPtr row, const Consts<T> &c) {
     return rhs5(P[fy][fx], P[fy][fx - 1], P[fy][fx + 1], P[fy - 1][fx], P[fy + 1][fx], u, v, gzx,
                 gzy, row, c);
 }
@@ -146,6 +146,8 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     __shared__ T C[FHM][kFW];
     extern __shared__ __attribute__((aligned(32))) double dyn_smem[];
     T *tab = reinterpret_cast<T *>(dyn_smem);
+    // the same table through an LDS pointer: 32-bit row addresses
+    const lds_t<T> *tab3 = (const lds_t<T> *)tab;
 
     const int tyi = tile / a.tiles_x;
     const int txi = tile - tyi * a.tiles_x;
@@ -244,20 +246,21 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     // ---- step 2a: first Heun stage on the tile plus two rings,
     // psi* = psi^n + dt F(psi^n)
     // the per-cell inputs of row k + 1 are loaded while row k computes
-    Inputs<T> nxt;
+    // (rows outside the stage load the domain's first cell instead, unused:
+    // unconditional loads need no register copies)
     auto in1 = [&](int k) {
         const int fy = ty + kNR * k;
         return xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi;
     };
-    if (in1(0)) nxt = load_inputs<SMALL>(idx0, cat, uw, vw, dzdx, dzdy);
+    auto src1 = [&](int k) { return in1(k) ? idx0 + (uint32_t)k * rstep : cbase; };
+    Inputs<T> nxt = load_inputs<SMALL>(src1(0), cat, uw, vw, dzdx, dzdy);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         const Inputs<T> cur = nxt;
-        if (k + 1 < KR && in1(k + 1))
-            nxt = load_inputs<SMALL>(idx0 + (uint32_t)(k + 1) * rstep, cat, uw, vw, dzdx, dzdy);
+        if (k + 1 < KR) nxt = load_inputs<SMALL>(src1(k + 1), cat, uw, vw, dzdx, dzdy);
         if (in1(k)) {
-            const T *row = tab + min((uint32_t)cur.cv, ncm1) * (uint32_t)kLRow;
+            const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cur.cv, ncm1), (uint32_t)kLRow);
             const T F1 = rhs(A, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
             B[fy][tx] = p0[k] + dt * F1;
         }
@@ -282,17 +285,17 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         const int fy = ty + kNR * k;
         return xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi;
     };
-    if (in2(0)) nxt = load_inputs<SMALL>(idx0, cat, uw, vw, dzdx, dzdy);
+    auto src2 = [&](int k) { return in2(k) ? idx0 + (uint32_t)k * rstep : cbase; };
+    nxt = load_inputs<SMALL>(src2(0), cat, uw, vw, dzdx, dzdy);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         const Inputs<T> cur = nxt;
-        if (k + 1 < KR && in2(k + 1))
-            nxt = load_inputs<SMALL>(idx0 + (uint32_t)(k + 1) * rstep, cat, uw, vw, dzdx, dzdy);
+        if (k + 1 < KR) nxt = load_inputs<SMALL>(src2(k + 1), cat, uw, vw, dzdx, dzdy);
         if (in2(k)) {
             const int gy = y0 - kHalo + fy;
             const uint32_t idx = idx0 + (uint32_t)k * rstep;
-            const T *row = tab + min((uint32_t)cur.cv, ncm1) * (uint32_t)kLRow;
+            const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cur.cv, ncm1), (uint32_t)kLRow);
             const T F2 = rhs(B, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
             const T pn0 = A[fy][tx];
             const T pn = T(0.5) * (pn0 + B[fy][tx]) + hdt * F2;
@@ -345,15 +348,16 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         const int fy = ty + kNR * k;
         return xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi;
     };
-    T fo_next = T(1);   // F of row k + 1 is loaded while row k computes
-    if (in3(0)) fo_next = at<SMALL>(frac, idx0);
+    // F of row k + 1 is loaded while row k computes
+    auto src3 = [&](int k) { return in3(k) ? idx0 + (uint32_t)k * rstep : cbase; };
+    T fo_next = at<SMALL>(frac, src3(0));
 #pragma unroll
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         T fs = T(0);
         fl[k] = T(0);
         const T fo = fo_next;
-        if (k + 1 < KR && in3(k + 1)) fo_next = at<SMALL>(frac, idx0 + (uint32_t)(k + 1) * rstep);
+        if (k + 1 < KR) fo_next = at<SMALL>(frac, src3(k + 1));
         if (in3(k)) {
             const uint32_t idx = idx0 + (uint32_t)k * rstep;
             T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
@@ -363,7 +367,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
             // was already below 1
             if (mn < T(0) || !(fo == T(1))) {
                 const int cv = at<SMALL>(cat, idx);
-                const T *row = tab + min((uint32_t)cv, ncm1) * (uint32_t)kLRow;
+                const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cv, ncm1), (uint32_t)kLRow);
                 T Fn = T(1);
                 if (mn < T(0)) Fn = cell_fraction(A, C, fy, tx, tp, row[kLTf]);
                 const T dF = (fo - Fn) * rdt;

@@ -9,11 +9,12 @@
 //    z_f from the piecewise-linear interpolant in ln z through (ln z0, 0)
 //    and the level values above z0 (0 if z_f <= z0, the top value above the
 //    highest level).  Computed in double.
-// 2. k_wind_bilinear, one thread per fire cell: bilinear interpolation of
-//    each component from its staggered points, coordinates clamped to the
-//    points' extent, in the array precision.  The kernel writes 2 values per
-//    fire cell and reads a field ~sr_x sr_y times smaller (from cache), so it
-//    is bound by the HBM writes.
+// 2. k_wind_bilinear, one fire row per work-group: bilinear interpolation
+//    of each component from its staggered points, coordinates clamped to
+//    the points' extent, in the array precision -- first in y, once per
+//    point of the row's span (into LDS), then in x per fire cell.  The kernel
+//    writes 2 values per fire cell and reads fields ~sr_x sr_y times smaller,
+//    so it is bound by the HBM writes.
 #include <cmath>
 
 #include "fire_internal.h"
@@ -129,50 +130,67 @@ template <typename T> __device__ __forceinline__ Axis<T> axis(int N, int Dn, T r
     return r;
 }
 
-template <typename T>
-__device__ __forceinline__ T bilin(const T *f, int fnx, const Axis<T> &x, const Axis<T> &y) {
-    const T *r0 = f + (size_t)y.k0 * fnx, *r1 = f + (size_t)y.k1 * fnx;
-    return (T(1) - x.t) * (T(1) - y.t) * r0[x.k0] + x.t * (T(1) - y.t) * r0[x.k1] +
-           (T(1) - x.t) * y.t * r1[x.k0] + x.t * y.t * r1[x.k1];
-}
+// One fire row per work-group, in chunks of kWChunk cells.  Per chunk the
+// y-interpolation is done once per staggered point the chunk spans, into a
+// line in LDS (the y weights are the same along the row); each thread then
+// interpolates 4 consecutive cells in x from that line and, when rows are
+// 4-aligned, stores them as one 16-byte vector.  A fire centre is at
+// x/DX = (i + 1/2)/sr_x; u-points at (I, J + 1/2), v-points at (I + 1/2, J)
+// in atmosphere-cell units.  Arithmetic in the array precision.
+constexpr int kWChunk = 4 * kWB;
+// staggered points a chunk can span: (kWChunk - 1)/sr_x + 3 at most
+constexpr int kWLine = kWChunk + 4;
 
-// One fire row per work-group (the y weights are the same along it); each
-// thread makes 4 consecutive cells and, when rows are 4-aligned, stores them
-// as one 16-byte vector.  A fire centre is at x/DX = (i + 1/2)/sr_x;
-// u-points at (I, J + 1/2), v-points at (I + 1/2, J) in atmosphere-cell
-// units.  Arithmetic in the array precision.
 template <typename T> struct alignas(4 * sizeof(T)) W4 { T a, b, c, d; };
 
 template <typename T>
 __global__ void __launch_bounds__(kWB)
 k_wind_bilinear(const WindArgs a, const T *uf, const T *vf, T *u, T *v) {
+    __shared__ T Lu[kWLine], Lv[kWLine];
     const int j = blockIdx.x;
     const int Dx = 2 * a.sr_x, Dy = 2 * a.sr_y;
     const T rx = T(a.rsx) * T(0.5), ry = T(a.rsy) * T(0.5);
     // x/DX = (2i + 1) / (2 sr_x), shifted by -1/2 (= -sr_x / (2 sr_x)) for v
     const Axis<T> uy = axis(2 * j + 1 - a.sr_y, Dy, ry, a.nay);
     const Axis<T> vy = axis(2 * j + 1, Dy, ry, a.nay + 1);
+    const T *u0 = uf + (size_t)uy.k0 * (a.nax + 1), *u1 = uf + (size_t)uy.k1 * (a.nax + 1);
+    const T *v0 = vf + (size_t)vy.k0 * a.nax, *v1 = vf + (size_t)vy.k1 * a.nax;
     const size_t row = (size_t)j * a.nx;
     const bool vec = a.vec != 0;
-    for (int i0 = 4 * threadIdx.x; i0 < a.nx; i0 += 4 * kWB) {
-        T ou[4], ov[4];
+    for (int c0 = 0; c0 < a.nx; c0 += kWChunk) {
+        const int c1 = (c0 + kWChunk < a.nx ? c0 + kWChunk : a.nx) - 1;
+        // point ranges [ub, ue], [vb, ve] of the chunk's cells
+        const int ub = axis(2 * c0 + 1, Dx, rx, a.nax + 1).k0;
+        const int ue = axis(2 * c1 + 1, Dx, rx, a.nax + 1).k1;
+        const int vb = axis(2 * c0 + 1 - a.sr_x, Dx, rx, a.nax).k0;
+        const int ve = axis(2 * c1 + 1 - a.sr_x, Dx, rx, a.nax).k1;
+        for (int q = threadIdx.x; q <= ue - ub && q < kWLine; q += kWB)
+            Lu[q] = (T(1) - uy.t) * u0[ub + q] + uy.t * u1[ub + q];
+        for (int q = threadIdx.x; q <= ve - vb && q < kWLine; q += kWB)
+            Lv[q] = (T(1) - vy.t) * v0[vb + q] + vy.t * v1[vb + q];
+        __syncthreads();
+        const int i0 = c0 + 4 * threadIdx.x;
+        if (i0 < a.nx) {
+            T ou[4], ov[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int i = i0 + q < a.nx ? i0 + q : a.nx - 1;
-            const Axis<T> ux = axis(2 * i + 1, Dx, rx, a.nax + 1);
-            const Axis<T> vx = axis(2 * i + 1 - a.sr_x, Dx, rx, a.nax);
-            ou[q] = bilin(uf, a.nax + 1, ux, uy);
-            ov[q] = bilin(vf, a.nax, vx, vy);
-        }
-        if (vec) {
-            *reinterpret_cast<W4<T> *>(u + row + i0) = W4<T>{ou[0], ou[1], ou[2], ou[3]};
-            *reinterpret_cast<W4<T> *>(v + row + i0) = W4<T>{ov[0], ov[1], ov[2], ov[3]};
-        } else {
-            for (int q = 0; q < 4 && i0 + q < a.nx; q++) {
-                u[row + i0 + q] = ou[q];
-                v[row + i0 + q] = ov[q];
+            for (int q = 0; q < 4; q++) {
+                const int i = i0 + q < a.nx ? i0 + q : a.nx - 1;
+                const Axis<T> ux = axis(2 * i + 1, Dx, rx, a.nax + 1);
+                const Axis<T> vx = axis(2 * i + 1 - a.sr_x, Dx, rx, a.nax);
+                ou[q] = (T(1) - ux.t) * Lu[ux.k0 - ub] + ux.t * Lu[ux.k1 - ub];
+                ov[q] = (T(1) - vx.t) * Lv[vx.k0 - vb] + vx.t * Lv[vx.k1 - vb];
+            }
+            if (vec) {
+                *reinterpret_cast<W4<T> *>(u + row + i0) = W4<T>{ou[0], ou[1], ou[2], ou[3]};
+                *reinterpret_cast<W4<T> *>(v + row + i0) = W4<T>{ov[0], ov[1], ov[2], ov[3]};
+            } else {
+                for (int q = 0; q < 4 && i0 + q < a.nx; q++) {
+                    u[row + i0 + q] = ou[q];
+                    v[row + i0 + q] = ov[q];
+                }
             }
         }
+        __syncthreads();
     }
 }
 

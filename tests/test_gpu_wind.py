@@ -4,8 +4,10 @@ staggered faces -> surface wind on the fire mesh, against the FP64 oracle.
 FP64: every fire cell within 1e-12 of the oracle (relative to the largest
 speed); FP32 (inputs rounded to float32 for both sides): within 2e-6.
 Shapes cover ragged fire meshes (not a multiple of the refinement), one
-atmosphere row or column, one level, roughness above z_f, and the
-8192 x 8192 mesh under 820 x 820 x 40 atmosphere cells on sampled cells.
+atmosphere row or column, one level, roughness above z_f, fire rows of
+several 1024-cell chunks (refinement 1, 7, 10; a chunk spanning the most
+staggered points), and the 8192 x 8192 mesh under 820 x 820 x 40
+atmosphere cells on sampled cells.
 """
 from __future__ import annotations
 
@@ -43,8 +45,11 @@ def _cast(atm, dt):
                          ids=["f64", "f32"])
 @pytest.mark.parametrize("shape", [(9, 7, 10, 10, 10, 86, 70), (5, 1, 4, 3, 4, 14, 4),
                                    (1, 6, 3, 5, 2, 5, 11), (3, 3, 1, 10, 10, 30, 30),
-                                   (12, 8, 20, 4, 6, 47, 45)],
-                         ids=["9x7x10", "row", "column", "one-level", "ragged"])
+                                   (12, 8, 20, 4, 6, 47, 45), (150, 4, 3, 10, 1, 1500, 4),
+                                   (1100, 2, 2, 1, 1, 1100, 2), (1100, 2, 2, 1, 1, 1099, 2),
+                                   (300, 3, 2, 7, 1, 2050, 3)],
+                         ids=["9x7x10", "row", "column", "one-level", "ragged", "wide-sr10",
+                              "wide-sr1", "wide-sr1-ragged", "wide-sr7"])
 def test_wind_matches_oracle(dt, tol, shape):
     nax, nay, nz, sr_x, sr_y, nx, ny = shape
     atm = synth.atmosphere(nax, nay, nz=nz, dx=6.0 * sr_x, dy=6.0 * sr_y, seed=nax * 100 + nay)

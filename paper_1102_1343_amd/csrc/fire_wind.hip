@@ -134,14 +134,14 @@ template <typename T> __device__ __forceinline__ Axis<T> axis(int N, int Dn, T r
 // y-interpolation is done once per staggered point the chunk spans, into a
 // line in LDS (the y weights are the same along the row); each thread then
 // interpolates 4 consecutive cells in x from that line and, when rows are
-// 4-aligned, stores them as one 16-byte vector.  A fire centre is at
+// 4-aligned, stores them as one 16-byte non-temporal vector.  A fire centre is at
 // x/DX = (i + 1/2)/sr_x; u-points at (I, J + 1/2), v-points at (I + 1/2, J)
 // in atmosphere-cell units.  Arithmetic in the array precision.
 constexpr int kWChunk = 4 * kWB;
 // staggered points a chunk can span: (kWChunk - 1)/sr_x + 3 at most
 constexpr int kWLine = kWChunk + 4;
 
-template <typename T> struct alignas(4 * sizeof(T)) W4 { T a, b, c, d; };
+template <typename T> using W4 = T __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __global__ void __launch_bounds__(kWB)
@@ -180,9 +180,10 @@ k_wind_bilinear(const WindArgs a, const T *uf, const T *vf, T *u, T *v) {
                 ou[q] = (T(1) - ux.t) * Lu[ux.k0 - ub] + ux.t * Lu[ux.k1 - ub];
                 ov[q] = (T(1) - vx.t) * Lv[vx.k0 - vb] + vx.t * Lv[vx.k1 - vb];
             }
-            if (vec) {
-                *reinterpret_cast<W4<T> *>(u + row + i0) = W4<T>{ou[0], ou[1], ou[2], ou[3]};
-                *reinterpret_cast<W4<T> *>(v + row + i0) = W4<T>{ov[0], ov[1], ov[2], ov[3]};
+            if (vec) {   // streaming (non-temporal) stores: the output is not re-read here
+                const W4<T> wu = {ou[0], ou[1], ou[2], ou[3]}, wv = {ov[0], ov[1], ov[2], ov[3]};
+                __builtin_nontemporal_store(wu, reinterpret_cast<W4<T> *>(u + row + i0));
+                __builtin_nontemporal_store(wv, reinterpret_cast<W4<T> *>(v + row + i0));
             } else {
                 for (int q = 0; q < 4 && i0 + q < a.nx; q++) {
                     u[row + i0 + q] = ou[q];

@@ -176,6 +176,14 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     // the per-row multiply is uniform (scalar) work
     const uint32_t idx0 = off0 + (uint32_t)ty * unx;
     const uint32_t rstep = (uint32_t)kNR * unx;
+    // k rstep held in a scalar register the compiler cannot see into (an
+    // empty asm): a full-rate vector add per row rather than a 64-bit
+    // multiply-add rebuilt from nx
+    auto roff = [&](int k) {
+        uint32_t r = (uint32_t)k * rstep;
+        asm("" : "+s"(r));
+        return r;
+    };
 
     for (int i = tid; i < a.ncat; i += kBlock)
         make_row(coef + i * kNCoef, tab + i * kLRow, T(a.ros_cap));
@@ -203,7 +211,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     for (int k = 0; k < KR; k++) {
         const int fy = ty + kNR * k;
         const bool in = colin && fy >= ylo && fy < yhi;
-        p0[k] = in ? at<SMALL>(psi_in, idx0 + (uint32_t)k * rstep) : T(0);
+        p0[k] = in ? at<SMALL>(psi_in, idx0 + roff(k)) : T(0);
         tig[k] = INF;
     }
     if (a.nign > 0) {
@@ -252,7 +260,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         const int fy = ty + kNR * k;
         return xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi;
     };
-    auto src1 = [&](int k) { return in1(k) ? idx0 + (uint32_t)k * rstep : cbase; };
+    auto src1 = [&](int k) { return in1(k) ? idx0 + roff(k) : cbase; };
     Inputs<T> nxt = load_inputs<SMALL>(src1(0), cat, uw, vw, dzdx, dzdy);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
@@ -285,7 +293,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         const int fy = ty + kNR * k;
         return xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi;
     };
-    auto src2 = [&](int k) { return in2(k) ? idx0 + (uint32_t)k * rstep : cbase; };
+    auto src2 = [&](int k) { return in2(k) ? idx0 + roff(k) : cbase; };
     nxt = load_inputs<SMALL>(src2(0), cat, uw, vw, dzdx, dzdy);
 #pragma unroll
     for (int k = 0; k < KR; k++) {
@@ -294,7 +302,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         if (k + 1 < KR) nxt = load_inputs<SMALL>(src2(k + 1), cat, uw, vw, dzdx, dzdy);
         if (in2(k)) {
             const int gy = y0 - kHalo + fy;
-            const uint32_t idx = idx0 + (uint32_t)k * rstep;
+            const uint32_t idx = idx0 + roff(k);
             const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cur.cv, ncm1), (uint32_t)kLRow);
             const T F2 = rhs(B, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
             const T pn0 = A[fy][tx];
@@ -349,7 +357,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         return xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi;
     };
     // F of row k + 1 is loaded while row k computes
-    auto src3 = [&](int k) { return in3(k) ? idx0 + (uint32_t)k * rstep : cbase; };
+    auto src3 = [&](int k) { return in3(k) ? idx0 + roff(k) : cbase; };
     T fo_next = at<SMALL>(frac, src3(0));
 #pragma unroll
     for (int k = 0; k < KR; k++) {
@@ -359,7 +367,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         const T fo = fo_next;
         if (k + 1 < KR) fo_next = at<SMALL>(frac, src3(k + 1));
         if (in3(k)) {
-            const uint32_t idx = idx0 + (uint32_t)k * rstep;
+            const uint32_t idx = idx0 + roff(k);
             T mn = vmin(vmin(A[fy - 1][tx - 1], A[fy - 1][tx]), A[fy - 1][tx + 1]);
             mn = vmin(mn, vmin(vmin(A[fy][tx - 1], A[fy][tx]), A[fy][tx + 1]));
             mn = vmin(mn, vmin(vmin(A[fy + 1][tx - 1], A[fy + 1][tx]), A[fy + 1][tx + 1]));

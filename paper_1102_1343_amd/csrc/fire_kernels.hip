@@ -215,13 +215,23 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         tig[k] = INF;
     }
     if (a.nign > 0) {
+        // each ignition's geometry at t, once per work-group (lane g of the
+        // first wave takes ignition g), shared through LDS
+        __shared__ IgnGeo<T> geo_s[FIRE_MAX_IGNITIONS];
+        __shared__ int geo_on[FIRE_MAX_IGNITIONS];
+        if (tid < a.nign) {
+            IgnGeo<T> gs;
+            geo_on[tid] = ign_setup<T>(ign[tid], tnow, gs) ? 1 : 0;
+            geo_s[tid] = gs;
+        }
+        __syncthreads();
         T pold[KR];
 #pragma unroll
         for (int k = 0; k < KR; k++) pold[k] = p0[k];
         const double xg = ((double)gx + 0.5) * a.dx;
         for (int g = 0; g < a.nign; g++) {
-            IgnGeo<T> geo;
-            if (!ign_setup<T>(ign[g], tnow, geo)) continue;
+            if (!geo_on[g]) continue;
+            const IgnGeo<T> geo = geo_s[g];
             const T px = T(xg - geo.ax);
 #pragma unroll
             for (int k = 0; k < KR; k++) {

@@ -157,9 +157,9 @@ def main():
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(several GPUs would each own a 2-D block of the fire mesh with a halo "
-              "exchange every step, which is not built)", file=sys.stderr)
+        print(f"bench.py: the fire step runs on one GPU; --gpus {args.gpus} is not "
+              "supported (several GPUs would each own a 2-D block of the fire mesh with a "
+              "halo exchange every step, which is not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -219,9 +219,40 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         // first wave takes ignition g), shared through LDS
         __shared__ IgnGeo<T> geo_s[FIRE_MAX_IGNITIONS];
         __shared__ int geo_on[FIRE_MAX_IGNITIONS];
+        __shared__ T wave_max[kBlock / 64];
+        // the frame's largest psi^n (NaN nodes, which no ignition changes,
+        // are ignored): an ignition whose psi_g is provably positive and no
+        // smaller than that on every frame node changes nothing here
+        T m = -INF;
+#pragma unroll
+        for (int k = 0; k < KR; k++) m = vmax(m, p0[k]);
+        for (int off = 32; off > 0; off >>= 1) m = vmax(m, __shfl_xor(m, off));
+        if ((tid & 63) == 0) wave_max[tid >> 6] = m;
+        __syncthreads();
         if (tid < a.nign) {
             IgnGeo<T> gs;
-            geo_on[tid] = ign_setup<T>(ign[tid], tnow, gs) ? 1 : 0;
+            bool on = ign_setup<T>(ign[tid], tnow, gs);
+            if (on) {
+                T M = wave_max[0];
+                for (int w = 1; w < kBlock / 64; w++) M = vmax(M, wave_max[w]);
+                // lower bound of psi_g over the frame nodes: distance from the
+                // frame's centre to the segment, less its half diagonal, the
+                // radius and a margin far above the rounding of psi_g
+                const double bx0 = (x0 - kHalo + 0.5) * a.dx;
+                const double bx1 = (x0 - kHalo + kFW - 0.5) * a.dx;
+                const double by0 = (y0 - kHalo + 0.5) * a.dy;
+                const double by1 = (y0 - kHalo + FHM - 0.5) * a.dy;
+                const double cx = 0.5 * (bx0 + bx1) - gs.ax, cy = 0.5 * (by0 + by1) - gs.ay;
+                const double ex = gs.ex, ey = gs.ey, L2 = ex * ex + ey * ey;
+                double sp = L2 > 0.0 ? (cx * ex + cy * ey) / L2 : 0.0;
+                sp = sp < 0.0 ? 0.0 : (sp > 1.0 ? 1.0 : sp);
+                const double qx = cx - sp * ex, qy = cy - sp * ey;
+                const double d = ::sqrt(qx * qx + qy * qy);
+                const double hd = 0.5 * ::sqrt((bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0));
+                const double lb = d - hd - (double)gs.rad - (1.0 + 1e-4 * (d + ::sqrt(L2)));
+                if (lb > 0.0 && lb >= (double)M) on = false;
+            }
+            geo_on[tid] = on ? 1 : 0;
             geo_s[tid] = gs;
         }
         __syncthreads();

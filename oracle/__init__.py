@@ -26,6 +26,12 @@ NONFINITE = 2
 S0, R0, B, CC, D, E, M, TF, CH, CQ = range(10)
 NCOEF = 10
 
+# intermediates of the Table 2 chain, in the order oracle_rothermel_terms
+# writes them (English units: 1/ft, lb/ft^2, ft, lb/ft^3, BTU/lb, ft/min)
+ROTHERMEL_TERMS = ("sigma", "w_l", "delta", "rho_P", "h", "w_0", "rho_b", "beta", "beta_op",
+                   "A", "Gamma_max", "Gamma", "w_n", "eta_M", "eta_s", "I_R", "xi", "epsilon",
+                   "Q_ig", "R0_ftmin", "R0_ms", "C", "B", "E", "U_a", "phi_W", "phi_S", "S_ms")
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle into ``liboracle_fire.so`` (gcc, -O3, OpenMP).
@@ -71,6 +77,9 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.oracle_coef.argtypes = [C.POINTER(_Fuel), C.c_int, C.c_double, dp]
         L.oracle_ros_product.argtypes = [C.POINTER(_Fuel), C.c_double, C.c_double, C.c_double, dp]
+        L.oracle_rothermel_terms.argtypes = [C.POINTER(_Fuel), C.c_double, C.c_double,
+                                             C.c_double, dp]
+        L.oracle_nterms.restype = C.c_int
         L.oracle_ros.argtypes = [dp, C.c_double, C.c_double, C.c_double]
         L.oracle_ros.restype = C.c_double
         L.oracle_extrapolate.argtypes = [dp, C.c_int, C.c_int, dp]
@@ -92,6 +101,7 @@ def lib():
         assert L.oracle_sizeof_fuel() == C.sizeof(_Fuel)
         assert L.oracle_sizeof_ign() == C.sizeof(_Ign)
         assert L.oracle_ncoef() == NCOEF
+        assert L.oracle_nterms() == len(ROTHERMEL_TERMS)
         _lib = L
     return _lib
 
@@ -144,6 +154,17 @@ def ros_product(f, U, tanphi, wind_cap=30.0) -> float:
     out = C.c_double()
     lib().oracle_ros_product(_fuels([f]), float(U), float(tanphi), float(wind_cap), C.byref(out))
     return out.value
+
+
+def rothermel_terms(f, U, tanphi, wind_cap=30.0) -> dict:
+    """Every intermediate of the Table 2 chain for fuel ``f`` (a non-chaparral
+    fuel record) at the 6.1 m wind U (m/s) and slope tan(phi)."""
+    out = np.zeros(len(ROTHERMEL_TERMS))
+    rc = lib().oracle_rothermel_terms(_fuels([f]), float(U), float(tanphi), float(wind_cap),
+                                      _dptr(out))
+    if rc != len(ROTHERMEL_TERMS):
+        raise ValueError("oracle_rothermel_terms failed (chaparral fuel?)")
+    return dict(zip(ROTHERMEL_TERMS, out.tolist()))
 
 
 def extrapolate(psi: np.ndarray) -> np.ndarray:

@@ -9,12 +9,11 @@
  * library never links it, and the two share no source, header or table.
  *
  * Every step is written as plain loops over the fire mesh, in double
- * precision, in the order the paper gives in Sect. 6 ("the fire model then
- * makes one time step"): (1) ignition, (2) Heun step of the level-set
- * equation, (3) ignition times, (4) fuel fraction, (5) heat fluxes,
- * (6) averaging onto the atmosphere mesh, plus the boundary check of
- * Sect. 4.1.  OpenMP only splits independent per-cell loops, so results do
- * not depend on the thread count.
+ * precision, in the order Sect. 6 gives for one time step of the fire model:
+ * (1) ignition, (2) Heun step of the level-set equation, (3) ignition times,
+ * (4) fuel fraction, (5) heat fluxes, (6) averaging onto the atmosphere mesh,
+ * plus the boundary check of Sect. 4.1.  OpenMP only splits independent
+ * per-cell loops, so results do not depend on the thread count.
  *
  * Where the paper is silent or garbled the reading used is stated at the
  * point of use and tagged R1..R28, one tag per reading, so the same choice can
@@ -26,11 +25,13 @@
  *                                  scheme identity max(D-^+,D+^-)
  *   oracle_ros (coefficient form)  pinned: chaparral values of Eq. (2);
  *                                  equality with the product form Eq. (1)
- *   oracle_coef (Rothermel chain)  PARTIAL -- "parity unpinned" for the
- *                                  absolute value of R0: the paper prints no
- *                                  worked spread rate.  Pinned only by
- *                                  special cases (extinction moisture gives
- *                                  R0 = 0, linearity in h, T_f(w) of Eq. (4))
+ *   rothermel_chain / oracle_coef  pinned: every intermediate of Table 2
+ *   (Rothermel chain, Table 2)     (sigma ... R0, C, B, E, phi_W, phi_S, S)
+ *                                  against a hand evaluation of the printed
+ *                                  formulas for two fuels
+ *                                  (tests/golden/rothermel_table2.txt), limit
+ *                                  cases of readings R1/R2, extinction
+ *                                  moisture (R0 = 0), linearity in h
  *   level set (Heun/Godunov/ROS)   pinned: planar-front closed form, circle
  *                                  r0 + S t convergence, Heun time order
  *   ignition time Eq. (14)         pinned: planar-front closed form
@@ -116,20 +117,69 @@ int oracle_sizeof_ign(void) { return (int)sizeof(of_ign); }
 #define L_COND 2.5e6
 
 /*
+ * The spread-rate chain of Sect. 2.2 / Table 2 for one (non-chaparral) fuel,
+ * every intermediate kept.  The fuel data are first converted to English
+ * units (Table 2 caption: lb, ft, min, BTU), then the table's rows are
+ * evaluated in dependency order.  Readings where the table is garbled:
+ * Gamma_max uses 0.0594 (R1); Q_ig = 250 + 1116 M_f (R2); beta_op =
+ * 3.348 sigma^-0.8189 and B = 0.02526 sigma^0.54, Rothermel's definitions the
+ * table uses without printing (R4); the moisture ratio is capped at 1 so
+ * eta_M >= 0 (R15).  The wind and slope factors, which also depend on U and
+ * tan(phi), are evaluated by the callers.
+ */
+typedef struct {
+    double sigma, wl, delta, rhoP, h;           /* inputs in English units       */
+    double w0, rhob, beta, beta_op, A, Gmax, Gamma, wn, etaM, etas, IR, xi, eps_h, Qig;
+    double R0_ftmin;                            /* no-wind, no-slope rate, ft/min */
+    double C, B, E;                             /* wind-factor constants          */
+} rothermel;
+
+static void rothermel_chain(const of_fuel *f, rothermel *o)
+{
+    double Mf = f->fuelmc_g;
+    /* English units: lb/ft^2, ft, 1/ft, lb/ft^3, BTU/lb */
+    o->wl = f->fgi * M_PER_FT * M_PER_FT / KG_PER_LB;
+    o->delta = f->fueldepthm / M_PER_FT;
+    o->sigma = f->savr * M_PER_FT;
+    o->rhoP = f->fueldens * M_PER_FT * M_PER_FT * M_PER_FT / KG_PER_LB;
+    o->h = f->cmbcnst * KG_PER_LB / J_PER_BTU;
+
+    double sigma = o->sigma;
+    o->w0 = o->wl / (1.0 + Mf);                      /* load net of moisture (CAWFE) */
+    o->rhob = o->w0 / o->delta;                      /* oven-dry bulk density        */
+    o->beta = o->rhob / o->rhoP;                     /* packing ratio                */
+    o->beta_op = 3.348 * pow(sigma, -0.8189);        /* optimum packing ratio (R4)   */
+    o->A = 1.0 / (4.77 * pow(sigma, 0.1) - 7.27);
+    double s15 = pow(sigma, 1.5);
+    o->Gmax = s15 / (495.0 + 0.0594 * s15);          /* (R1) */
+    double rat = o->beta / o->beta_op;
+    o->Gamma = o->Gmax * pow(rat, o->A) * exp(o->A * (1.0 - rat));
+    o->wn = o->w0 / (1.0 + f->st);                   /* net of minerals */
+    double r = Mf / f->fuelmce;
+    if (r > 1.0) r = 1.0;                            /* (R15) */
+    o->etaM = 1.0 - 2.59 * r + 5.11 * r * r - 3.52 * r * r * r;
+    o->etas = 0.174 * pow(f->se, -0.19);
+    o->IR = o->Gamma * o->wn * o->h * o->etaM * o->etas;   /* reaction intensity */
+    o->xi = exp((0.792 + 0.681 * sqrt(sigma)) * (o->beta + 0.1)) / (192.0 + 0.2595 * sigma);
+    o->eps_h = exp(-138.0 / sigma);                  /* effective heating number */
+    o->Qig = 250.0 + 1116.0 * Mf;                    /* (R2) */
+    o->R0_ftmin = o->IR * o->xi / (o->rhob * o->eps_h * o->Qig);
+
+    o->C = 7.47 * exp(-0.133 * pow(sigma, 0.55));
+    o->B = 0.02526 * pow(sigma, 0.54);               /* (R4) */
+    o->E = 0.715 * exp(-3.59e-4 * sigma);
+}
+
+/*
  * Per-category spread-rate coefficients, Sect. 2.2 and Table 2.
  *
- * The fuel data are first converted to English units (Table 2 caption), the
- * no-wind rate R0 follows the chain of Table 2, and the wind and slope
+ * The no-wind rate R0 comes from the chain above, and the wind and slope
  * factors of Eq. (1) are folded into the coefficient form Eq. (3):
  *   R0*phi_W = c * U^b   with U the 6.1 m wind in m/s (clamped to [0, e]),
- *   R0*phi_S = d * tan^2(phi).
- * Readings (Table 2 is garbled in places): Gamma_max uses 0.0594 (R1);
- * Q_ig = 250 + 1116 M_f (R2); phi_W = C (a U)^B (beta/beta_op)^(-E) (R3);
- * beta_op = 3.348 sigma^-0.8189 and B = 0.02526 sigma^0.54, Rothermel's
- * definitions that the table uses without printing (R4); the moisture ratio
- * is capped at 1 so eta_M >= 0 (R15).  Chaparral (Eq. 2) is written in the
- * coefficient form with S0 = 0.03333, R0 = 0, b = 1, c = 1.2974, d = 0,
- * e = 6/1.2974.
+ *   R0*phi_S = d * tan^2(phi),
+ * where phi_W = C (a U)^B (beta/beta_op)^(-E) with a U in ft/min (R3).
+ * Chaparral (Eq. 2) is written in the coefficient form with S0 = 0.03333,
+ * R0 = 0, b = 1, c = 1.2974, d = 0, e = 6/1.2974.
  *
  * Also tabulated: T_f from Eq. (4) (T_f = -600 w / (1000 ln 0.6) when tf<=0),
  * the sensible-flux factor w_l h/(1+M_f) of Eq. (5) and the latent factor
@@ -158,53 +208,69 @@ int oracle_coef(const of_fuel *fu, int ncat, double wind_cap, double *tab)
             continue;
         }
 
-        /* English units: lb/ft^2, ft, 1/ft, lb/ft^3, BTU/lb */
-        double wl = f->fgi * M_PER_FT * M_PER_FT / KG_PER_LB;
-        double delta = f->fueldepthm / M_PER_FT;
-        double sigma = f->savr * M_PER_FT;
-        double rhoP = f->fueldens * M_PER_FT * M_PER_FT * M_PER_FT / KG_PER_LB;
-        double h = f->cmbcnst * KG_PER_LB / J_PER_BTU;
-
-        double w0 = wl / (1.0 + Mf);                    /* load net of moisture (CAWFE) */
-        double rhob = w0 / delta;                       /* oven-dry bulk density        */
-        double beta = rhob / rhoP;                      /* packing ratio                */
-        double beta_op = 3.348 * pow(sigma, -0.8189);   /* optimum packing ratio (R4)   */
-        double A = 1.0 / (4.77 * pow(sigma, 0.1) - 7.27);
-        double s15 = pow(sigma, 1.5);
-        double Gmax = s15 / (495.0 + 0.0594 * s15);     /* (R1) */
-        double rat = beta / beta_op;
-        double Gamma = Gmax * pow(rat, A) * exp(A * (1.0 - rat));
-        double wn = w0 / (1.0 + f->st);                 /* net of minerals */
-        double r = Mf / f->fuelmce;
-        if (r > 1.0) r = 1.0;                           /* (R15) */
-        double etaM = 1.0 - 2.59 * r + 5.11 * r * r - 3.52 * r * r * r;
-        double etas = 0.174 * pow(f->se, -0.19);
-        double IR = Gamma * wn * h * etaM * etas;       /* reaction intensity */
-        double xi = exp((0.792 + 0.681 * sqrt(sigma)) * (beta + 0.1)) / (192.0 + 0.2595 * sigma);
-        double eps_h = exp(-138.0 / sigma);             /* effective heating number */
-        double Qig = 250.0 + 1116.0 * Mf;               /* (R2) */
-        double R0_ftmin = IR * xi / (rhob * eps_h * Qig);
-
-        double C = 7.47 * exp(-0.133 * pow(sigma, 0.55));
-        double B = 0.02526 * pow(sigma, 0.54);           /* (R4) */
-        double E = 0.715 * exp(-3.59e-4 * sigma);
-
-        double R0 = R0_ftmin * MS_PER_FTMIN;
+        rothermel q;
+        rothermel_chain(f, &q);
+        double rat = q.beta / q.beta_op;
+        double R0 = q.R0_ftmin * MS_PER_FTMIN;
         row[OC_S0] = 0.0;                               /* (R14) */
         row[OC_R0] = R0;
-        row[OC_B] = B;
+        row[OC_B] = q.B;
         /* R0*phi_W = R0*C*(beta/beta_op)^-E * (a*U/MS_PER_FTMIN)^B  (R3) */
-        row[OC_C] = R0 * C * pow(rat, -E) * pow(f->windrf / MS_PER_FTMIN, B);
-        row[OC_D] = R0 * 5.275 * pow(beta, -0.3);
+        row[OC_C] = R0 * q.C * pow(rat, -q.E) * pow(f->windrf / MS_PER_FTMIN, q.B);
+        row[OC_D] = R0 * 5.275 * pow(q.beta, -0.3);
         row[OC_E] = wind_cap;
     }
     return 0;
 }
 
+/* Intermediates of the chain as written out by oracle_rothermel_terms(). */
+enum {
+    ORT_SIGMA, ORT_WL, ORT_DELTA, ORT_RHOP, ORT_H, ORT_W0, ORT_RHOB, ORT_BETA, ORT_BETA_OP,
+    ORT_A, ORT_GMAX, ORT_GAMMA, ORT_WN, ORT_ETAM, ORT_ETAS, ORT_IR, ORT_XI, ORT_EPS, ORT_QIG,
+    ORT_R0_FTMIN, ORT_R0_MS, ORT_C, ORT_B, ORT_E, ORT_UA, ORT_PHIW, ORT_PHIS, ORT_S_MS, ORT_N
+};
+
+int oracle_nterms(void) { return ORT_N; }
+
 /*
- * Product form Eq. (1), S = R0 (1 + phi_W + phi_S), with the wind and slope
- * factors of Table 2 evaluated directly (not through the coefficients).  Only
- * the tests call this: it pins the coefficient form of Eq. (3).
+ * Product form Eq. (1), S = R0 (1 + phi_W + phi_S), with the wind factor
+ * phi_W = C U_a^B (beta/beta_op)^(-E) (R3), U_a = a U in ft/min at midflame
+ * (U clamped to [0, wind_cap], Table 2 caption), and the slope factor
+ * phi_S = 5.275 beta^-0.3 tan^2(phi) (tan(phi) >= 0), evaluated directly
+ * rather than through the coefficients.  Writes every intermediate of Table 2
+ * (ORT_* order) to out[ORT_N] and returns ORT_N; the tests pin these values
+ * against a hand evaluation of the printed formulas.  Chaparral fuels have no
+ * chain (returns -1).
+ */
+int oracle_rothermel_terms(const of_fuel *f, double U, double tanphi, double wind_cap,
+                           double *out)
+{
+    if (!f || !out || f->ichap) return -1;
+    rothermel q;
+    rothermel_chain(f, &q);
+    double R0 = q.R0_ftmin;                                       /* ft/min */
+    double Uc = fmin(wind_cap, fmax(0.0, U));                     /* m/s, clamped */
+    double Ua = f->windrf * Uc / MS_PER_FTMIN;                    /* midflame ft/min */
+    double phiW = q.C * pow(Ua, q.B) * pow(q.beta / q.beta_op, -q.E);
+    double tp = fmax(0.0, tanphi);
+    double phiS = 5.275 * pow(q.beta, -0.3) * tp * tp;
+    out[ORT_SIGMA] = q.sigma;  out[ORT_WL] = q.wl;  out[ORT_DELTA] = q.delta;
+    out[ORT_RHOP] = q.rhoP;  out[ORT_H] = q.h;  out[ORT_W0] = q.w0;  out[ORT_RHOB] = q.rhob;
+    out[ORT_BETA] = q.beta;  out[ORT_BETA_OP] = q.beta_op;  out[ORT_A] = q.A;
+    out[ORT_GMAX] = q.Gmax;  out[ORT_GAMMA] = q.Gamma;  out[ORT_WN] = q.wn;
+    out[ORT_ETAM] = q.etaM;  out[ORT_ETAS] = q.etas;  out[ORT_IR] = q.IR;  out[ORT_XI] = q.xi;
+    out[ORT_EPS] = q.eps_h;  out[ORT_QIG] = q.Qig;  out[ORT_R0_FTMIN] = R0;
+    out[ORT_R0_MS] = R0 * MS_PER_FTMIN;
+    out[ORT_C] = q.C;  out[ORT_B] = q.B;  out[ORT_E] = q.E;  out[ORT_UA] = Ua;
+    out[ORT_PHIW] = phiW;  out[ORT_PHIS] = phiS;
+    out[ORT_S_MS] = f->ros_mult * R0 * (1.0 + phiW + phiS) * MS_PER_FTMIN;
+    return ORT_N;
+}
+
+/*
+ * Product form Eq. (1) as a spread rate (m/s), with the per-category
+ * multiplier; chaparral fuels use Eq. (2).  Only the tests call this: it pins
+ * the coefficient form of Eq. (3).
  */
 int oracle_ros_product(const of_fuel *f, double U, double tanphi, double wind_cap,
                        double *S_out)
@@ -217,37 +283,9 @@ int oracle_ros_product(const of_fuel *f, double U, double tanphi, double wind_ca
         *S_out = s * f->ros_mult;
         return 0;
     }
-    double Mf = f->fuelmc_g;
-    double wl = f->fgi * M_PER_FT * M_PER_FT / KG_PER_LB;
-    double delta = f->fueldepthm / M_PER_FT;
-    double sigma = f->savr * M_PER_FT;
-    double rhoP = f->fueldens * M_PER_FT * M_PER_FT * M_PER_FT / KG_PER_LB;
-    double h = f->cmbcnst * KG_PER_LB / J_PER_BTU;
-    double w0 = wl / (1.0 + Mf);
-    double rhob = w0 / delta;
-    double beta = rhob / rhoP;
-    double beta_op = 3.348 * pow(sigma, -0.8189);
-    double A = 1.0 / (4.77 * pow(sigma, 0.1) - 7.27);
-    double Gmax = pow(sigma, 1.5) / (495.0 + 0.0594 * pow(sigma, 1.5));
-    double Gamma = Gmax * pow(beta / beta_op, A) * exp(A * (1.0 - beta / beta_op));
-    double wn = w0 / (1.0 + f->st);
-    double r = fmin(Mf / f->fuelmce, 1.0);
-    double etaM = 1.0 - 2.59 * r + 5.11 * r * r - 3.52 * r * r * r;
-    double etas = 0.174 * pow(f->se, -0.19);
-    double IR = Gamma * wn * h * etaM * etas;
-    double xi = exp((0.792 + 0.681 * sqrt(sigma)) * (beta + 0.1)) / (192.0 + 0.2595 * sigma);
-    double Qig = 250.0 + 1116.0 * Mf;
-    double R0 = IR * xi / (rhob * exp(-138.0 / sigma) * Qig);      /* ft/min */
-
-    double Uc = fmin(wind_cap, fmax(0.0, U));                     /* m/s, clamped */
-    double Ua = f->windrf * Uc / MS_PER_FTMIN;                    /* midflame ft/min */
-    double C = 7.47 * exp(-0.133 * pow(sigma, 0.55));
-    double B = 0.02526 * pow(sigma, 0.54);
-    double E = 0.715 * exp(-3.59e-4 * sigma);
-    double phiW = C * pow(Ua, B) * pow(beta / beta_op, -E);
-    double tp = fmax(0.0, tanphi);
-    double phiS = 5.275 * pow(beta, -0.3) * tp * tp;
-    *S_out = f->ros_mult * R0 * (1.0 + phiW + phiS) * MS_PER_FTMIN;
+    double t[ORT_N];
+    oracle_rothermel_terms(f, U, tanphi, wind_cap, t);
+    *S_out = t[ORT_S_MS];
     return 0;
 }
 

@@ -49,6 +49,86 @@ def test_coefficient_form_equals_product_form():
                 assert a == pytest.approx(b, rel=1e-13), (k, U, tp)
 
 
+def _table2_cases():
+    """Fuels and hand-worked Table 2 intermediates from golden/rothermel_table2.txt."""
+    fuels, terms = {}, {}
+    for ln in open(os.path.join(GOLD, "rothermel_table2.txt")):
+        ln = ln.split("#")[0].strip()
+        if not ln:
+            continue
+        w = ln.split()
+        if w[0] == "fuel":
+            kv = dict(x.split("=") for x in w[2:])
+            U, tp = float(kv.pop("U")), float(kv.pop("tanphi"))
+            fuels[w[1]] = (synth.fuel(**{k: float(v) for k, v in kv.items()}), U, tp)
+        else:
+            terms.setdefault(w[0], {})[w[1]] = float(w[2])
+    return [(fuels[k][0], fuels[k][1], fuels[k][2], terms[k]) for k in sorted(fuels)]
+
+
+def test_rothermel_table2_golden():
+    """Every intermediate of the Table 2 chain (unit conversion, w_0 ... R0,
+    C, B, E, U_a, phi_W, phi_S, S of Eq. 1) equals a hand evaluation of the
+    printed formulas (readings R1-R4) for two fuels that differ in every
+    input.  A change of any constant of the chain moves at least one term by
+    far more than the tolerance."""
+    cases = _table2_cases()
+    assert len(cases) == 2
+    for f, U, tp, want in cases:
+        got = oracle.rothermel_terms(f, U, tp)
+        assert set(want) == set(oracle.ROTHERMEL_TERMS)
+        for name in oracle.ROTHERMEL_TERMS:
+            assert got[name] == pytest.approx(want[name], rel=1e-12), name
+
+
+def test_rothermel_coefficients_fold_the_chain():
+    """The coefficient form Eq. (3) carries the chain's values: R0 in m/s,
+    b = B, c U^b = R0 phi_W and d tan^2(phi) = R0 phi_S at the golden winds and
+    slopes, and S of Eq. (3) equals S = R0 (1 + phi_W + phi_S) of Eq. (1)."""
+    for f, U, tp, want in _table2_cases():
+        row = oracle.coef([f])[0]
+        R0 = want["R0_ms"]
+        assert row[oracle.R0] == pytest.approx(R0, rel=1e-12)
+        assert row[oracle.B] == pytest.approx(want["B"], rel=1e-12)
+        assert row[oracle.CC] * U ** row[oracle.B] == pytest.approx(R0 * want["phi_W"], rel=1e-12)
+        assert row[oracle.D] * tp * tp == pytest.approx(R0 * want["phi_S"], rel=1e-12)
+        assert oracle.ros(row, U, tp) == pytest.approx(want["S_ms"], rel=1e-12)
+
+
+def test_rothermel_reading_limits():
+    """Limits that tell the readings apart: Gamma_max tends to 1/0.0594 as
+    sigma grows (R1; 1/0.594 under the printed constant), Q_ig is 250 BTU/lb
+    for dry fuel and grows by 1116 per unit moisture (R2; 250 beta + 1116 M_f
+    would vanish for dry fuel), the heating number exp(-138/sigma) tends to 1,
+    and beta_op, B follow Rothermel's power laws in sigma (R4)."""
+    big = oracle.rothermel_terms(synth.fuel(savr=1e13), 0.0, 0.0)
+    assert big["Gamma_max"] == pytest.approx(1.0 / 0.0594, rel=1e-9)
+    assert big["epsilon"] == pytest.approx(1.0, rel=1e-9)
+    dry = oracle.rothermel_terms(synth.fuel(fuelmc_g=0.0), 0.0, 0.0)
+    wet = oracle.rothermel_terms(synth.fuel(fuelmc_g=0.1), 0.0, 0.0)
+    assert dry["Q_ig"] == 250.0
+    assert wet["Q_ig"] == pytest.approx(250.0 + 111.6, rel=1e-15)
+    for savr in (3000.0, 8000.0, 12000.0):
+        t = oracle.rothermel_terms(synth.fuel(savr=savr), 0.0, 0.0)
+        s = savr * 0.3048
+        assert t["beta_op"] == pytest.approx(3.348 * s ** -0.8189, rel=1e-14)
+        assert t["B"] == pytest.approx(0.02526 * s ** 0.54, rel=1e-14)
+        # no wind, no slope: Eq. (1) reduces to R0
+        assert t["phi_W"] == 0.0 and t["phi_S"] == 0.0
+        assert t["S_ms"] == pytest.approx(t["R0_ms"], rel=1e-15)
+
+
+def test_rothermel_validation_fuel_rough_values():
+    """The validation workload's fuel, rounded: R0 about 0.0273 m/s,
+    b about 1.704 and S about 0.492 m/s at a normal wind of 2 m/s on flat
+    ground (three significant digits, a check against gross slips that is
+    independent of the golden file's digits)."""
+    row = oracle.coef([synth.fuel(fgi=0.5, fueldepthm=0.5, fuelmc_g=0.08, savr=8000.0)])[0]
+    assert round(row[oracle.R0], 4) == 0.0273
+    assert round(row[oracle.B], 3) == 1.704
+    assert round(oracle.ros(row, 2.0, 0.0), 3) == 0.492
+
+
 def test_rothermel_special_cases():
     """Exact special cases of the Table 2 chain: at the moisture of extinction
     eta_M vanishes (its cubic sums to zero) so R0 = 0; the reaction intensity

@@ -60,7 +60,7 @@ enum { FIRE_STATUS_BOUNDARY = 1, FIRE_STATUS_NONFINITE = 2 };
 typedef enum { FIRE_F32 = 0, FIRE_F64 = 1 } fire_dtype;
 
 /* Fire mesh (Sect. 3): nx x ny cells of dx x dy metres; sr_x x sr_y fire
- * cells make one atmosphere cell (refinement ratio, Sect. 8.2).  Needs
+ * cells make one atmosphere cell (refinement ratio, Sect. 8.3).  Needs
  * nx, ny >= 2, 1 <= sr_x <= 122, 1 <= sr_y <= 26. */
 typedef struct {
     int32_t nx, ny;
@@ -157,10 +157,19 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
  * flux_sens / flux_lat (device atmosphere arrays) and updates the state in
  * the arena.  If out is not NULL it receives device pointers to the new
  * psi, t_i and F (valid until the next fire_step) and the new time.
- * With boundary_policy 0 the call waits for the step and returns
- * FIRE_ERR_BOUNDARY if fire reached the guard ring; later calls then do
- * nothing and return FIRE_ERR_BOUNDARY.  With policy 1 nothing waits and the
- * condition is only recorded in the status word.
+ *
+ * Boundary policy 0 (Sect. 4.1: the run terminates when fire reaches the
+ * guard ring): after each step the status word is copied to pinned host
+ * memory on the stream, and each call reads the copies of earlier steps
+ * before enqueueing its own -- the copy of the step before the last is
+ * waited for (so the host runs at most one step ahead of what it has
+ * checked), the last one only if it has already completed.  When a copy
+ * shows fire in the guard ring the call enqueues nothing and returns
+ * FIRE_ERR_BOUNDARY, or FIRE_ERR_NONFINITE for a non-finite psi or F; every
+ * later call returns the same code without stepping.  The state then holds
+ * the step that set the bit or at most one step more; fire_status() (which
+ * waits) reports the bits exactly and also stops the run.  With policy 1
+ * nothing waits and the conditions are only recorded in the status word.
  */
 int fire_step(fire_ctx *ctx, const void *u, const void *v, double dt, void *flux_sens,
               void *flux_lat, fire_view *out);
@@ -173,8 +182,15 @@ int fire_get_state(fire_ctx *ctx, fire_view *out);
 int fire_set_state(fire_ctx *ctx, const void *psi, const void *tign, const void *frac, double t);
 
 /* Waits for the context's stream and returns the sticky FIRE_STATUS_* bits
- * (>= 0), or a negative error code. */
+ * (>= 0), or a negative error code.  Under boundary policy 0 a set bit also
+ * stops later fire_step() calls. */
 int fire_status(fire_ctx *ctx);
+
+/* The tile shape fire_init() picks for this mesh (host only, no device
+ * call): the widest multiple of sr_x up to 122 columns and the tallest
+ * multiple of sr_y up to 20 rows (sr_y itself when sr_y > 20), within the
+ * limits of fire_set_tile().  FIRE_ERR_ARG for an invalid mesh. */
+int fire_default_tile(const fire_mesh *mesh, int32_t *tile_x, int32_t *tile_y);
 
 /* Copies the per-category coefficient table to host memory (waits):
  * out[ncat][10] as doubles, columns S0 R0 b c d e m T_f C_h C_q. */
@@ -203,8 +219,9 @@ void fire_destroy(fire_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * Ensemble: many independent fire domains of different sizes advanced by one
- * kernel launch per step (the data-parallel use of Sect. 9: many fire
- * simulations, each the method of fire_step() unchanged).  Every member
+ * kernel launch per step (the data-parallel use that ensemble data
+ * assimilation makes of the model, Sect. 11.5: many fire simulations, each
+ * the method of fire_step() unchanged).  Every member
  * computes exactly what a single-domain context with the same mesh, fuels,
  * ignitions and parameters computes, bit for bit, whatever the tile shape.
  *

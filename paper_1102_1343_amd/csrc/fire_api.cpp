@@ -58,13 +58,14 @@ bool ignitions_ok(const fire_ignition *ign, int nign) {
 }
 
 // default tile: widest multiple of sr_x that fits the frame, and the
-// tallest multiple of sr_y up to 20 rows (26 when sr_y does not divide 20)
+// tallest multiple of sr_y up to 20 rows; when sr_y > 20 the one multiple
+// sr_y itself (mesh_ok keeps sr_y within the FP64 frame limit)
 void default_tile(const fire_mesh *m, int *tx, int *ty) {
     *tx = (kTileXMax / m->sr_x) * m->sr_x;
+    const int ymax = m->dtype == FIRE_F64 ? kTileYMax64 : kTileYMax;
     int best = 0;
-    for (int h = m->sr_y; h <= kTileYMax; h += m->sr_y)
-        if (h <= 20) best = h;
-    if (best == 0) best = (kTileYMax / m->sr_y) * m->sr_y;
+    for (int h = m->sr_y; h <= ymax; h += m->sr_y)
+        if (h <= 20 || best == 0) best = h;
     *ty = best;
 }
 
@@ -248,7 +249,31 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
     c->t = prm->t0;
     c->stream = (hipStream_t)stream;
     c->stopped = 0;
+    c->host_status = nullptr;
+    c->ev[0] = c->ev[1] = nullptr;
+    c->ev_valid[0] = c->ev_valid[1] = 0;
+    c->nstep = 0;
     default_tile(mesh, &c->tile_x, &c->tile_y);
+    if (!tile_ok(mesh, c->tile_x, c->tile_y)) {
+        delete c;
+        return FIRE_ERR_ARG;
+    }
+    if (prm->boundary_policy == 0) {
+        // pinned host slots for the lagging status copies (host memory; the
+        // library still allocates no device memory)
+        void *hs = nullptr;
+        if (hipHostMalloc(&hs, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+            delete c;
+            return FIRE_ERR_HIP;
+        }
+        c->host_status = (int32_t *)hs;
+        c->host_status[0] = c->host_status[1] = 0;
+        if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+            fire_destroy(c);
+            return FIRE_ERR_HIP;
+        }
+    }
 
     // the fuel table goes through the arena (it may exceed kernel-argument
     // space); the copy is synchronous because cats is pageable host memory
@@ -270,19 +295,61 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
         e = launch_fill(mesh->dtype, state_ptr(c, L.psi0), state_ptr(c, L.tign),
                         state_ptr(c, L.frac), (size_t)mesh->nx * mesh->ny, psi0, c->stream);
     if (e != hipSuccess) {
-        delete c;
+        fire_destroy(c);
         return FIRE_ERR_HIP;
     }
     *out = c;
     return FIRE_OK;
 }
 
+namespace {
+
+// Stop policy: the status a completed copy reports, as an error code (0 if
+// neither bit is set).
+int status_code(int32_t st) {
+    if (st & FIRE_STATUS_BOUNDARY) return FIRE_ERR_BOUNDARY;
+    if (st & FIRE_STATUS_NONFINITE) return FIRE_ERR_NONFINITE;
+    return FIRE_OK;
+}
+
+// Reads the lagging status copies: the one of the step before the last is
+// waited for (so at most one step is in flight beyond what has been checked),
+// the last one only if it has completed.  Returns an error code to stop with,
+// FIRE_OK, or FIRE_ERR_HIP.
+int check_lagged(fire_ctx *c) {
+    for (int back = 1; back >= 0; back--) {
+        const long k = c->nstep - 1 - back;   // step whose copy sits in slot k % 2
+        if (k < 0) continue;
+        const int slot = (int)(k % 2);
+        if (!c->ev_valid[slot]) continue;
+        hipError_t e = back == 1 ? hipEventSynchronize(c->ev[slot]) : hipEventQuery(c->ev[slot]);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return FIRE_ERR_HIP;
+        c->ev_valid[slot] = 0;
+        const int code = status_code(c->host_status[slot]);
+        if (code != FIRE_OK) return code;
+    }
+    return FIRE_OK;
+}
+
+}  // namespace
+
 int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_sens,
               void *flux_lat, fire_view *out) {
     if (!c || !u || !v || !flux_sens || !flux_lat) return FIRE_ERR_ARG;
     if (!(dt > 0.0) || !std::isfinite(dt)) return FIRE_ERR_ARG;
-    if (c->stopped) return FIRE_ERR_BOUNDARY;
-    const fire_mesh &m = c->mesh;
+    if (c->stopped) return c->stopped;
+    if (c->prm.boundary_policy == 0) {
+        // Sect. 4.1: the run terminates when fire reaches the boundary.  The
+        // condition is read from copies of the status word lagging by at most
+        // one step, so the host never waits for the step it just enqueued.
+        const int code = check_lagged(c);
+        if (code == FIRE_ERR_HIP) return code;
+        if (code != FIRE_OK) {
+            c->stopped = code;
+            return code;
+        }
+    }
 
     hipError_t e = step_raw(c, state_ptr(c, c->off_psi[c->cur]),
                             state_ptr(c, c->off_psi[1 - c->cur]), state_ptr(c, c->off_tign),
@@ -298,14 +365,14 @@ int fire_step(fire_ctx *c, const void *u, const void *v, double dt, void *flux_s
         out->t = c->t;
     }
     if (c->prm.boundary_policy == 0) {
-        // Sect. 4.1: the run terminates when fire reaches the boundary
-        int st = fire_status(c);
-        if (st < 0) return st;
-        if (st & FIRE_STATUS_BOUNDARY) {
-            c->stopped = 1;
-            return FIRE_ERR_BOUNDARY;
-        }
+        const int slot = (int)(c->nstep % 2);
+        e = hipMemcpyAsync(&c->host_status[slot], state_ptr(c, c->off_status), sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[slot], c->stream);
+        if (e != hipSuccess) return FIRE_ERR_HIP;
+        c->ev_valid[slot] = 1;
     }
+    c->nstep++;
     return FIRE_OK;
 }
 
@@ -333,6 +400,7 @@ int fire_set_state(fire_ctx *c, const void *psi, const void *tign, const void *f
     if (e != hipSuccess) return FIRE_ERR_HIP;
     c->t = t;
     c->stopped = 0;
+    c->ev_valid[0] = c->ev_valid[1] = 0;   // copies of the old status are not read
     return FIRE_OK;
 }
 
@@ -343,7 +411,20 @@ int fire_status(fire_ctx *c) {
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return FIRE_ERR_HIP;
-    return st & (FIRE_STATUS_BOUNDARY | FIRE_STATUS_NONFINITE);
+    st &= FIRE_STATUS_BOUNDARY | FIRE_STATUS_NONFINITE;
+    if (c->prm.boundary_policy == 0 && !c->stopped && status_code(st) != FIRE_OK)
+        c->stopped = status_code(st);   // the stop policy holds from here on
+    return st;
+}
+
+int fire_default_tile(const fire_mesh *mesh, int32_t *tile_x, int32_t *tile_y) {
+    if (!mesh_ok(mesh) || !tile_x || !tile_y) return FIRE_ERR_ARG;
+    int tx, ty;
+    default_tile(mesh, &tx, &ty);
+    if (!tile_ok(mesh, tx, ty)) return FIRE_ERR_ARG;
+    *tile_x = tx;
+    *tile_y = ty;
+    return FIRE_OK;
 }
 
 int fire_coef(fire_ctx *c, double *out, int32_t ncat) {
@@ -389,6 +470,15 @@ int fire_set_stream(fire_ctx *c, void *stream) {
     return FIRE_OK;
 }
 
-void fire_destroy(fire_ctx *c) { delete c; }
+void fire_destroy(fire_ctx *c) {
+    if (!c) return;
+    for (int i = 0; i < 2; i++)
+        if (c->ev[i]) {
+            if (c->ev_valid[i]) hipEventSynchronize(c->ev[i]);   // copy into host_status
+            hipEventDestroy(c->ev[i]);
+        }
+    if (c->host_status) hipHostFree(c->host_status);
+    delete c;
+}
 
 }  // extern "C"

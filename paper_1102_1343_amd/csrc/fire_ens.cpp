@@ -188,6 +188,10 @@ int fire_ens_init(fire_ens **out, const fire_mesh *meshes, int32_t ndom, const f
     e->dzdy = dzdy;
     e->stream = (hipStream_t)stream;
     default_tile(&meshes[0], &e->tile_x, &e->tile_y);
+    if (!tile_ok(&meshes[0], e->tile_x, e->tile_y)) {
+        delete e;
+        return FIRE_ERR_ARG;
+    }
 
     // ignition records padded to FIRE_MAX_IGNITIONS per domain
     std::vector<fire_ignition> &igs = e->ign_host;

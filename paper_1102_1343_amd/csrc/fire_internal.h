@@ -101,7 +101,15 @@ struct fire_ctx {
     double t;              // model time of the current state
     hipStream_t stream;
     int tile_x, tile_y;
-    int stopped;           // boundary reached under the stop policy
+    int stopped;           // FIRE_ERR_BOUNDARY / FIRE_ERR_NONFINITE once the stop
+                           // policy has seen that status bit, else 0
+    // Stop policy: after each step the status word is copied to pinned host
+    // memory (slot nstep % 2) and an event is recorded; the next call reads
+    // the copies that are complete, waiting only for the one two steps back.
+    int32_t *host_status;  // hipHostMalloc'd, 2 slots (null under policy 1)
+    hipEvent_t ev[2];
+    int ev_valid[2];
+    long nstep;
 };
 
 namespace fire {

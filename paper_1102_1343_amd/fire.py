@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfire_gfx950.so")
 FIRE_F32, FIRE_F64 = 0, 1
 STATUS_BOUNDARY, STATUS_NONFINITE = 1, 2
 ERR_BOUNDARY = -4
+ERR_NONFINITE = -5
 MAX_IGNITIONS = 8
 NCOEF = 10
 COEF_NAMES = ("S0", "R0", "b", "c", "d", "e", "m", "Tf", "Ch", "Cq")
@@ -91,6 +92,7 @@ def lib():
         L.fire_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
         L.fire_get_tile.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
         L.fire_set_stream.argtypes = [vp, vp]
+        L.fire_default_tile.argtypes = [P(fire_mesh), P(C.c_int32), P(C.c_int32)]
         L.fire_strerror.argtypes = [C.c_int]
         L.fire_strerror.restype = C.c_char_p
         L.fire_destroy.argtypes = [vp]
@@ -129,6 +131,16 @@ def lib():
     return _lib
 
 
+def default_tile(nx, ny, dx, dy, sr_x, sr_y, dtype=torch.float32):
+    """The tile shape a context for this mesh starts with (fire_default_tile;
+    host only)."""
+    m = fire_mesh(int(nx), int(ny), float(dx), float(dy), int(sr_x), int(sr_y),
+                  FIRE_F64 if dtype == torch.float64 else FIRE_F32, 0)
+    a, b = C.c_int32(), C.c_int32()
+    _check(lib().fire_default_tile(C.byref(m), C.byref(a), C.byref(b)), "fire_default_tile")
+    return a.value, b.value
+
+
 def strerror(code: int) -> str:
     return lib().fire_strerror(int(code)).decode()
 
@@ -155,6 +167,34 @@ def _ign_array(igns):
     return arr
 
 
+def _need(t, name, shape=None, dtype=None, device=None, numel=None):
+    """Raise ValueError unless ``t`` is a contiguous CUDA tensor on ``device``
+    with the given dtype and shape (or element count).  Runs before any
+    pointer reaches the library, which has no way to check them."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: expected a CUDA tensor, got one on {t.device}")
+    if device is not None and t.device != torch.device(device):
+        raise ValueError(f"{name}: expected a tensor on {device}, got one on {t.device}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    return t
+
+
+def _cuda_device(device):
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise ValueError(f"the fire library runs on a GPU; device {d} is not a CUDA device")
+    return torch.device("cuda", torch.cuda.current_device() if d.index is None else d.index)
+
+
 def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -179,7 +219,7 @@ class Fire:
         if len(ignitions) > MAX_IGNITIONS:
             raise ValueError(f"at most {MAX_IGNITIONS} ignitions")
         self.dtype = dtype
-        self.device = torch.device(device)
+        self.device = _cuda_device(device)
         self.nx, self.ny = int(nx), int(ny)
         self.nax = -(-self.nx // int(sr_x))
         self.nay = -(-self.ny // int(sr_y))
@@ -246,9 +286,12 @@ class Fire:
         as the third element."""
         if flux_sens is None or flux_lat is None:
             flux_sens, flux_lat = self.new_flux()
-        for t in (u, v):
-            if t.dtype != self.dtype or not t.is_contiguous() or t.shape != (self.ny, self.nx):
-                raise ValueError("wind must be contiguous [ny, nx] tensors of the fire dtype")
+        grid = (self.ny, self.nx)
+        _need(u, "u", grid, self.dtype, self.device)
+        _need(v, "v", grid, self.dtype, self.device)
+        atm = (self.nay, self.nax)
+        _need(flux_sens, "flux_sens", atm, self.dtype, self.device)
+        _need(flux_lat, "flux_lat", atm, self.dtype, self.device)
         rc = lib().fire_step(self._ctx, C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
                              float(dt), C.c_void_p(flux_sens.data_ptr()),
                              C.c_void_p(flux_lat.data_ptr()), None)
@@ -304,6 +347,10 @@ class Fire:
         return out
 
     def ros_eval(self, cat, un, tn):
+        n = un.numel() if isinstance(un, torch.Tensor) else -1
+        _need(un, "un", dtype=self.dtype, device=self.device)
+        _need(tn, "tn", dtype=self.dtype, device=self.device, numel=n)
+        _need(cat, "cat", dtype=torch.uint8, device=self.device, numel=n)
         S = torch.empty_like(un)
         _check(lib().fire_ros_eval(self._ctx, C.c_void_p(cat.data_ptr()),
                                    C.c_void_p(un.data_ptr()), C.c_void_p(tn.data_ptr()),
@@ -351,7 +398,7 @@ class FireEnsemble:
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
-        self.device = torch.device(device)
+        self.device = _cuda_device(device)
         self.ndom = len(members)
         fd = FIRE_F64 if dtype == torch.float64 else FIRE_F32
         self.meshes = (fire_mesh * self.ndom)()
@@ -435,13 +482,18 @@ class FireEnsemble:
     def step(self, u, v, dt, flux_sens=None, flux_lat=None):
         if flux_sens is None or flux_lat is None:
             flux_sens, flux_lat = self.new_flux()
-        for t in (u, v):
-            if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != self.ncells:
-                raise ValueError("wind must be contiguous concatenated tensors of the fire dtype")
+        self._check_wind(u, v)
+        natm = int(self.atm_off[-1])
+        _need(flux_sens, "flux_sens", dtype=self.dtype, device=self.device, numel=natm)
+        _need(flux_lat, "flux_lat", dtype=self.dtype, device=self.device, numel=natm)
         _check(lib().fire_ens_step(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
                                    float(dt), C.c_void_p(flux_sens.data_ptr()),
                                    C.c_void_p(flux_lat.data_ptr())), "fire_ens_step")
         return flux_sens, flux_lat
+
+    def _check_wind(self, u, v):
+        _need(u, "u", dtype=self.dtype, device=self.device, numel=self.ncells)
+        _need(v, "v", dtype=self.dtype, device=self.device, numel=self.ncells)
 
     def _view(self):
         vw = fire_view()
@@ -490,6 +542,7 @@ class FireEnsemble:
     def autotune(self, u, v, dt, candidates, reps=5):
         """Time each (tile_x, tile_y) candidate, keep the fastest; the state is
         left as it was.  Returns the chosen shape."""
+        self._check_wind(u, v)
         nb = lib().fire_ens_tune_bytes(self._h)
         scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
         base = scratch.data_ptr() + (-scratch.data_ptr()) % 256
@@ -537,9 +590,8 @@ class FireAdjoint:
 
     def forward(self, u, v, dt):
         f = self.fire
-        for t in (u, v):
-            if t.dtype != f.dtype or not t.is_contiguous() or t.shape != (f.ny, f.nx):
-                raise ValueError("wind must be contiguous [ny, nx] tensors of the fire dtype")
+        _need(u, "u", (f.ny, f.nx), f.dtype, f.device)
+        _need(v, "v", (f.ny, f.nx), f.dtype, f.device)
         self._wind = (u, v)     # the library keeps the pointers until backward
         _check(lib().fire_adj_forward(self._h, C.c_void_p(u.data_ptr()),
                                       C.c_void_p(v.data_ptr()), float(dt)), "fire_adj_forward")
@@ -547,8 +599,7 @@ class FireAdjoint:
 
     def backward(self, dF):
         f = self.fire
-        if dF.dtype != f.dtype or not dF.is_contiguous() or dF.shape != (f.ny, f.nx):
-            raise ValueError("dF must be a contiguous [ny, nx] tensor of the fire dtype")
+        _need(dF, "dF", (f.ny, f.nx), f.dtype, f.device)
         gu = torch.empty_like(dF)
         gv = torch.empty_like(dF)
         gm = np.zeros(f.ncat)
@@ -588,6 +639,9 @@ class FireRun(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u, v, mult, shift, prob, nsteps, every=50, dtype=torch.float64):
+        for name, t in (("u", u), ("v", v)):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+                raise ValueError(f"{name}: FireRun needs CUDA tensors (the run is on the GPU)")
         fuels = [dict(f, ros_mult=float(m)) for f, m in zip(prob.fuels, mult.tolist())]
         igns = shifted_ignitions(prob.ignitions, shift.detach().cpu().tolist())
         p = dict(prob.params)
@@ -622,18 +676,18 @@ def wind_interp(u3, v3, phi, hgt, z0, nx, ny, sr_x, sr_y, zf=6.1, g=9.81, stream
     tensors of one floating dtype).  Returns (u, v) device tensors (``out``
     if given).  With a caller-kept ``scratch`` (uint8 device tensor of at
     least wind_scratch_bytes() + 256) the call does not wait."""
-    dt = u3.dtype
+    _need(u3, "u3")
+    dt, dev = u3.dtype, u3.device
     if dt not in (torch.float32, torch.float64):
         raise ValueError("float32 or float64 tensors expected")
+    if u3.dim() != 3:
+        raise ValueError("u3: expected [nz, nay, nax + 1]")
     nz, nay, nax1 = u3.shape
     nax = nax1 - 1
     shapes = {"v3": (v3, (nz, nay + 1, nax)), "phi": (phi, (nz + 1, nay, nax)),
               "hgt": (hgt, (nay, nax)), "z0": (z0, (nay, nax))}
     for name, (t, shp) in shapes.items():
-        if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous():
-            raise ValueError(f"{name}: expected contiguous {shp} {dt}")
-    if not u3.is_contiguous():
-        raise ValueError("u3 must be contiguous")
+        _need(t, name, shp, dt, dev)
     grid = fire_wind_grid(nax, nay, nz, int(sr_x), int(sr_y), int(nx), int(ny),
                           FIRE_F64 if dt == torch.float64 else FIRE_F32, float(zf), float(g))
     nb = lib().fire_wind_scratch_bytes(C.byref(grid))
@@ -641,15 +695,19 @@ def wind_interp(u3, v3, phi, hgt, z0, nx, ny, sr_x, sr_y, zf=6.1, g=9.81, stream
         raise FireError(-1, "fire_wind_scratch_bytes")
     own = scratch is None
     if own:
-        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=u3.device)
-    elif scratch.numel() < nb + 256:
-        raise ValueError("scratch too small")
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+    else:
+        _need(scratch, "scratch", dtype=torch.uint8, device=dev)
+        if scratch.numel() < nb + 256:
+            raise ValueError("scratch too small")
     base = scratch.data_ptr() + (-scratch.data_ptr()) % 256
     if out is None:
-        u = torch.empty((int(ny), int(nx)), dtype=dt, device=u3.device)
+        u = torch.empty((int(ny), int(nx)), dtype=dt, device=dev)
         v = torch.empty_like(u)
     else:
         u, v = out
+        _need(u, "out[0]", (int(ny), int(nx)), dt, dev)
+        _need(v, "out[1]", (int(ny), int(nx)), dt, dev)
     _check(lib().fire_wind_interp(C.byref(grid), C.c_void_p(u3.data_ptr()),
                                   C.c_void_p(v3.data_ptr()), C.c_void_p(phi.data_ptr()),
                                   C.c_void_p(hgt.data_ptr()), C.c_void_p(z0.data_ptr()),

@@ -7,7 +7,7 @@ HIP path and the CPU oracle can both be fed from it.
 
 The recipes stand in for the paper's real-data cases (FireFlux, Meadow Creek,
 Sect. 10), whose data are not available: they keep the fire/atmosphere
-refinement ratio of 10 (Sect. 8.2), the 13 fuel categories (Sect. 2.1), a
+refinement ratio of 10 (Sect. 8.3), the 13 fuel categories (Sect. 2.1), a
 fire-cell size of a few metres and the 6.1 m wind (Sect. 6).
 
 Every generator takes an explicit ``numpy.random.Generator`` (PCG64) so that

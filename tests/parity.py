@@ -141,12 +141,13 @@ class Compare64:
 
 
 def front_error(psi_g, psi_ref, dx, dy):
-    """max over cells with |psi_ref| <= 2 dx of |dpsi| / max(|grad psi_ref|, 0.5), in cells."""
+    """max over cells with |psi_ref| <= 2 dx of |dpsi| / max(|grad psi_ref|, 0.5),
+    in cells.  Fails when no cell is that near the front: a front check with
+    nothing to check must not pass."""
     gy, gx = np.gradient(psi_ref, dy, dx)
     gn = np.maximum(np.hypot(gx, gy), 0.5)
     near = np.abs(psi_ref) <= 2 * max(dx, dy)
-    if not near.any():
-        return 0.0
+    assert near.any(), "no cell within 2 dx of the front"
     return float(np.max(np.abs(psi_g - psi_ref)[near] / gn[near]) / dx)
 
 

@@ -181,3 +181,50 @@ def test_ensemble_status_per_member():
     st = ens.status()
     assert st[2] & F.STATUS_BOUNDARY
     assert all(st[k] == 0 for k in (0, 1, 3)), st
+
+
+def test_ensemble256_members_bitwise_after_500_steps():
+    """The benchmark's ensemble (256 members of side 256-1024, 500 steps, FP32)
+    in the benchmark's launch configuration -- autotuned tile, one HIP-graph
+    replay per step -- against plain contexts on the same inputs, bit for bit,
+    for the smallest and largest members and two more."""
+    probs = synth.ensemble(ndom=256, side_min=256, side_max=1024, steps=500,
+                           field_dtype=np.float32)
+    steps = probs[0].steps
+    sides = np.array([p.nx * p.ny for p in probs])
+    pick = sorted({int(np.argmin(sides)), int(np.argmax(sides)), 97, 200})
+    _log(f"ensemble256: members {pick} (sides {[probs[k].nx for k in pick]})")
+    ens = F.FireEnsemble.from_problems(probs, dtype=torch.float32)
+    u, v = _ens_wind(ens, probs)
+    fs, fl = ens.new_flux()
+    tile = ens.autotune(u, v, probs[0].dt, [(120, 20), (120, 40), (60, 20)], reps=2)
+    stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    ens.set_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            ens.step(u, v, probs[0].dt, fs, fl)
+    ens.set_stream(stream)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    _log(f"tile {tile}, {steps} graph replays done")
+    ref = _plain_run([probs[k] for k in pick], torch.float32, steps)
+    st = ens.status()
+    for j, k in enumerate(pick):
+        psi, tig, frac, rfs, rfl, rst, rt = ref[j]
+        for name, a, b in (("psi", ens.member(ens.psi, k), psi),
+                           ("tign", ens.member(ens.tign, k), tig),
+                           ("frac", ens.member(ens.frac, k), frac),
+                           ("flux_sens", ens.member(fs, k, atm=True), rfs),
+                           ("flux_lat", ens.member(fl, k, atm=True), rfl)):
+            ia = a.contiguous().view(torch.int32)
+            ib = b.contiguous().view(torch.int32)
+            nbad = int((ia != ib).sum())
+            assert nbad == 0, f"member {k} {name}: {nbad} elements differ"
+        assert st[k] == rst
+        assert int((ref[j][2] < 1).sum()) > 100, f"member {k} has no burnt cells"
+    assert abs(ens.t - ref[0][6]) == 0.0
+    del graph

@@ -203,26 +203,48 @@ def test_checkpoint_resume_bitwise():
     assert a.t == b.t
 
 
-def test_boundary_stop_and_continue():
-    n, dx = 64, 6.0
+def _edge_problem(policy, n=64, dx=6.0):
     fz = np.zeros((n, n))
     edge = [synth.ignition(3.0, 200.0, t_start=0.0, radius=10.0)]
+    return synth.Problem(n, n, dx, dx, 10, 10, [synth.fuel()], np.zeros((n, n), np.uint8),
+                         fz, fz, edge, 0.5, 5, [(fz + 1.0, fz)], 0,
+                         dict(viscosity=0.4, boundary_policy=policy, guard_width=1))
+
+
+def test_boundary_stop_and_continue():
+    """Stop policy: fire_step reads status copies lagging by at most one
+    step, so the call after the step that reached the guard ring, or the one
+    after that, returns FIRE_ERR_BOUNDARY; from then on calls do nothing.
+    Continue policy: the bit is only recorded."""
+    n = 64
+    u = torch.ones((n, n), device="cuda")
+    v = torch.zeros((n, n), device="cuda")
     for policy in (0, 1):
-        prob = synth.Problem(n, n, dx, dx, 10, 10, [synth.fuel()], np.zeros((n, n), np.uint8),
-                             fz, fz, edge, 0.5, 5, [(fz + 1.0, fz)], 0,
-                             dict(viscosity=0.4, boundary_policy=policy, guard_width=1))
-        g = gpu_fire(prob, torch.float32)
-        u = torch.ones((n, n), device="cuda")
-        v = torch.zeros((n, n), device="cuda")
+        g = gpu_fire(_edge_problem(policy), torch.float32)
         _, _, rc = g.step(u, v, 0.5, check=False)
+        assert rc == 0
         if policy == 0:
+            calls = 1
+            while rc == 0:
+                _, _, rc = g.step(u, v, 0.5, check=False)
+                calls += 1
+                assert calls <= 3
             assert rc == F.ERR_BOUNDARY
-            psi_before = g.psi.clone()
+            psi_stop, t_stop = g.psi.clone(), g.t
+            assert t_stop <= 2 * 0.5          # the boundary step and at most one more
             _, _, rc2 = g.step(u, v, 0.5, check=False)
-            assert rc2 == F.ERR_BOUNDARY and torch.equal(psi_before, g.psi)
+            assert rc2 == F.ERR_BOUNDARY and torch.equal(psi_stop, g.psi) and g.t == t_stop
         else:
-            assert rc == 0
-            assert g.status() & F.STATUS_BOUNDARY
+            for _ in range(3):
+                _, _, rc = g.step(u, v, 0.5, check=False)
+                assert rc == 0
+        assert g.status() & F.STATUS_BOUNDARY
+    # fire_status (which waits) stops the run at once under the stop policy
+    g = gpu_fire(_edge_problem(0), torch.float32)
+    g.step(u, v, 0.5, check=False)
+    assert g.status() & F.STATUS_BOUNDARY
+    _, _, rc = g.step(u, v, 0.5, check=False)
+    assert rc == F.ERR_BOUNDARY and g.t == 0.5
     inside = synth.uniform_fire(64, steps=4)
     g = gpu_fire(inside, torch.float32)
     W = wind_tensors(inside, torch.float32)
@@ -233,14 +255,19 @@ def test_boundary_stop_and_continue():
 
 def test_nonfinite_state_is_reported():
     prob = synth.uniform_fire(48, steps=2)
-    g = gpu_fire(prob, torch.float32, boundary_policy=1)
     psi = torch.full((48, 48), 50.0, device="cuda")
     psi[20, 20] = float("nan")
-    g.set_state(psi, torch.full((48, 48), float("inf"), device="cuda"),
-                torch.ones((48, 48), device="cuda"), 0.0)
     W = wind_tensors(prob, torch.float32)
-    g.step(W[0][0], W[0][1], prob.dt)
-    assert g.status() & F.STATUS_NONFINITE
+    for policy in (1, 0):
+        g = gpu_fire(prob, torch.float32, boundary_policy=policy)
+        g.set_state(psi, torch.full((48, 48), float("inf"), device="cuda"),
+                    torch.ones((48, 48), device="cuda"), 0.0)
+        rcs = [g.step(W[0][0], W[0][1], prob.dt, check=False)[2] for _ in range(3)]
+        assert g.status() & F.STATUS_NONFINITE
+        if policy == 1:
+            assert rcs == [0, 0, 0]
+        else:
+            assert rcs[0] == 0 and F.ERR_NONFINITE in rcs[1:]
 
 
 def test_invalid_arguments_raise():
@@ -255,3 +282,17 @@ def test_invalid_arguments_raise():
         g.set_tile(120, 15)
     with pytest.raises(ValueError):
         g.step(W[0][0].double(), W[0][1].double(), 0.5)
+    fs, fl = g.new_flux()
+    with pytest.raises(ValueError, match="dtype"):
+        g.step(W[0][0], W[0][1], 0.5, fs.double(), fl.double())
+    with pytest.raises(ValueError, match="shape"):
+        g.step(W[0][0], W[0][1], 0.5, fs[:1], fl)
+    with pytest.raises(ValueError, match="CUDA"):
+        g.step(W[0][0].cpu(), W[0][1], 0.5, fs, fl)
+    with pytest.raises(ValueError, match="contiguous"):
+        g.step(W[0][0].t(), W[0][1], 0.5, fs, fl)
+    cat = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError, match="elements"):
+        g.ros_eval(cat, torch.zeros(8, device="cuda"), torch.zeros(7, device="cuda"))
+    with pytest.raises(ValueError, match="dtype"):
+        g.ros_eval(cat.int(), torch.zeros(8, device="cuda"), torch.zeros(8, device="cuda"))

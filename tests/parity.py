@@ -151,6 +151,120 @@ def front_error(psi_g, psi_ref, dx, dy):
     return float(np.max(np.abs(psi_g - psi_ref)[near] / gn[near]) / dx)
 
 
+def _vertices_at(psi, jj, ii):
+    """The nine sub-cell points (centre, edge midpoints, corners) of the listed
+    cells by bilinear interpolation, neighbours clamped at the domain edge;
+    shape [9, n]."""
+    ny, nx = psi.shape
+
+    def at(dj, di):
+        return psi[np.clip(jj + dj, 0, ny - 1), np.clip(ii + di, 0, nx - 1)]
+    c = at(0, 0)
+    out = [c]
+    for a in (-1, 1):
+        out.append(0.5 * (c + at(0, a)))
+        out.append(0.5 * (c + at(a, 0)))
+        for b in (-1, 1):
+            out.append(0.25 * (c + at(0, a) + at(b, 0) + at(b, a)))
+    return np.array(out)
+
+
+def vertex_min_abs_at(psi, jj, ii):
+    """subpoint_min_abs for the listed cells only (neighbours clamped at the
+    domain edge): the smallest |psi| over the nine sub-cell points of each."""
+    return np.min(np.abs(_vertices_at(psi, jj, ii)), axis=0)
+
+
+def knife_cells(psi_g, psi_o, near):
+    """Fire cells (jj, ii) where a sub-cell point of the oracle's psi lies
+    within that cell's own discrepancy between the two runs of zero (plus the
+    FP32 rounding of the interpolation): there the two runs may take opposite
+    sides of the Eq. (17) switch."""
+    jj, ii = np.nonzero(np.abs(psi_o) <= near)
+    if jj.size == 0:
+        return jj, ii
+    vo = _vertices_at(psi_o, jj, ii)
+    vg = _vertices_at(psi_g, jj, ii)
+    local = np.max(np.abs(vg - vo), axis=0)
+    scale = np.max(np.abs(vo), axis=0)
+    k = np.min(np.abs(vo), axis=0) <= 2.0 * local + 2.0 ** -20 * scale
+    return jj[k], ii[k]
+
+
+class FluxCompare32:
+    """Per-step FP32 total-flux check with knife edges set aside.
+
+    Eq. (17) resets the interpolated ignition time at a sub-cell vertex to t
+    where psi >= 0 there, so F of a cell jumps when one of its vertex values
+    crosses zero.  When the FP64 oracle's vertex value sits within the two
+    runs' local psi discrepancy of zero (knife_cells), they may take opposite
+    sides of that switch and F of that cell differs by a finite amount for
+    one step (the next step agrees again; the time integral telescopes).  The
+    per-step totals of step n leave out the flux of the fire cells that were
+    knife edges after step n or after step n - 1 -- each side's own
+    (F^n - F^{n+1})/dt times the cell's flux factor -- and those cells must
+    carry a small share of the flux.  The time-integrated totals use every
+    cell, as the atmosphere fluxes report them.
+    """
+
+    def __init__(self, prob, tab, near=None):
+        self.prob = prob
+        self.ch = tab[:, 8]                 # C_h, C_q per category (oracle table)
+        self.cq = tab[:, 9]
+        self.near = 2 * max(prob.dx, prob.dy) if near is None else near
+        self.prev = None                    # (jj, ii) knife cells after the previous step
+        self.prev_frac = None
+        self.rows, self.full, self.excl_frac, self.nknife = [], [], [], []
+
+    def step(self, psi_g, psi_o, frac_g, frac_o, fs_g, fl_g, fs_o, fl_o, dt):
+        pr = self.prob
+        jj, ii = knife_cells(psi_g, psi_o, self.near)
+        cells = set(zip(jj.tolist(), ii.tolist()))
+        if self.prev is not None:
+            cells |= set(zip(self.prev[0].tolist(), self.prev[1].tolist()))
+        nay, nax = fs_o.shape
+        cy = np.minimum(pr.sr_y, pr.ny - pr.sr_y * np.arange(nay))
+        cx = np.minimum(pr.sr_x, pr.nx - pr.sr_x * np.arange(nax))
+        area = np.outer(cy, cx) * pr.dx * pr.dy
+        full = [float(np.sum(f * area)) for f in (fs_g, fs_o, fl_g, fl_o)]
+        drop = [0.0, 0.0, 0.0, 0.0]
+        if cells and self.prev_frac is not None:
+            kj = np.array([c[0] for c in cells])
+            ki = np.array([c[1] for c in cells])
+            cat = np.asarray(pr.cat)[kj, ki]
+            a = pr.dx * pr.dy / dt
+            dg = (self.prev_frac[0][kj, ki] - frac_g[kj, ki]) * a
+            do = (self.prev_frac[1][kj, ki] - frac_o[kj, ki]) * a
+            drop = [float(np.sum(dg * self.ch[cat])), float(np.sum(do * self.ch[cat])),
+                    float(np.sum(dg * self.cq[cat])), float(np.sum(do * self.cq[cat]))]
+        self.rows.append([f - d for f, d in zip(full, drop)])
+        self.full.append(full)
+        self.excl_frac.append(abs(drop[1]) / abs(full[1]) if full[1] != 0 else 0.0)
+        self.nknife.append(len(cells))
+        self.prev = (jj, ii)
+        self.prev_frac = (frac_g.copy(), frac_o.copy())
+        return len(cells)
+
+    def check(self, what, log, rel_bar=1e-4):
+        rows, full = np.array(self.rows), np.array(self.full)
+        big = np.abs(full[:, 1]) > 1e-3 * np.max(np.abs(full[:, 1]))
+        assert big.sum() >= 10
+        ef = np.array(self.excl_frac)[big]
+        for j, name in ((0, "sensible"), (2, "latent")):
+            g, o = rows[big, j], rows[big, j + 1]
+            rel = np.abs(g - o) / np.abs(o)
+            fg, fo = full[:, j], full[:, j + 1]
+            raw = np.abs(fg[big] - fo[big]) / np.abs(fo[big])
+            integ = abs(fg.sum() - fo.sum()) / abs(fo.sum())
+            log(f"{what} {name}: max rel per step {rel.max():.2e} without knife-edge cells "
+                f"({raw.max():.2e} with them), integrated {integ:.2e}; knife-edge cells in "
+                f"{int(np.count_nonzero(np.array(self.nknife)[big]))}/{int(big.sum())} steps, "
+                f"at most {max(self.nknife)}, largest share of the flux {ef.max():.2e}")
+            assert rel.max() <= rel_bar
+            assert integ <= rel_bar
+        assert ef.max() <= 0.02, "knife-edge cells carry a large share of the flux"
+
+
 def total_flux(fs, prob):
     """Sum over atmosphere cells of flux * (fire cells in the cell) * dx dy."""
     nay, nax = fs.shape

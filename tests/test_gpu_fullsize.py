@@ -5,9 +5,11 @@
 the FP32-rounded inputs:
   * the whole mesh for the first 50 steps (all four ignitions start within
     them): total sensible and latent heat flux over the domain within 1e-4
-    relative per step (once above 1e-3 of its peak) and summed over the
-    steps, front position within 0.05 cell everywhere, F where no front is
-    near;
+    relative per step (once above 1e-3 of its peak; fire cells where a
+    sub-cell vertex of the oracle sits within the runs' local psi discrepancy
+    of the Eq. (17) switch are left out of that step, see
+    parity.FluxCompare32) and summed over the steps (every cell), front
+    position within 0.05 cell everywhere, F where no front is near;
   * after 120 steps, windows of 700 x 700 around the start and around the
     end of each ignition segment (every window has burning cells in its
     compared interior).  psi at a node after n steps depends only on psi^0
@@ -34,7 +36,7 @@ import torch
 import oracle
 from paper_1102_1343_amd import synth
 
-from parity import Compare64, front_error, gpu_fire, host, total_flux
+from parity import Compare64, FluxCompare32, front_error, gpu_fire, host, total_flux
 
 pytestmark = pytest.mark.gpu
 
@@ -64,34 +66,26 @@ def _gpu_run(prob, steps):
     return g, np.array(tot)
 
 
-def _check_totals(tot_g, tot_o, what):
-    for j in range(2):
-        peak = np.max(np.abs(tot_o[:, j]))
-        big_ = np.abs(tot_o[:, j]) > 1e-3 * peak
-        assert big_.sum() >= 10
-        rel = np.abs(tot_g[big_, j] - tot_o[big_, j]) / np.abs(tot_o[big_, j])
-        integ = abs(tot_g[:, j].sum() - tot_o[:, j].sum()) / abs(tot_o[:, j].sum())
-        _log(f"{what} flux {'sensible latent'.split()[j]}: max rel per step {rel.max():.2e} "
-             f"(step {int(np.nonzero(big_)[0][np.argmax(rel)])}), integrated {integ:.2e}")
-        assert rel.max() <= 1e-4
-        assert integ <= 1e-4
-
-
 def test_fullsize_8192_fp32_whole_domain(big):
     prob = big
     steps = 50
-    g, tot_g = _gpu_run(prob, steps)
-    psi_g, frac_g = host(g.psi), host(g.frac)
-    _log(f"gpu {steps} steps done, status {g.status()}")
+    W = [(torch.from_numpy(np.ascontiguousarray(u)).cuda(),
+          torch.from_numpy(np.ascontiguousarray(v)).cuda()) for u, v in prob.wind]
+    g = gpu_fire(prob, torch.float32)
+    assert g.get_tile() == (120, 20)
+    fs, fl = g.new_flux()
     p64 = prob.cast(np.float32)
     o = oracle.OracleFire(p64)
-    tot_o = []
+    cmp = FluxCompare32(prob, o.tab)
     for k in range(steps):
+        u, v = W[(k // prob.wind_period) % len(W)]
+        g.step(u, v, prob.dt, fs, fl)
         fs_o, fl_o = o.step(*p64.wind_at(k), prob.dt)
-        tot_o.append((total_flux(fs_o, prob), total_flux(fl_o, prob)))
-    tot_o = np.array(tot_o)
-    _log(f"oracle done; burning cells {(o.psi < 0).sum()}")
-    _check_totals(tot_g, tot_o, "8192^2")
+        cmp.step(host(g.psi), o.psi, host(g.frac), o.frac, host(fs), host(fl), fs_o, fl_o,
+                 prob.dt)
+    psi_g, frac_g = host(g.psi), host(g.frac)
+    _log(f"{steps} steps done, status {g.status()}, burning cells {(o.psi < 0).sum()}")
+    cmp.check("8192^2", _log)
     err = front_error(psi_g, o.psi, prob.dx, prob.dy)
     _log(f"front error {err:.2e} cells")
     assert err <= 0.05
@@ -155,31 +149,23 @@ def test_patchy2048_fp64_full_field():
 def test_fullsize_2048_fp32_full_length():
     prob = synth.patchy_fire(n=2048, steps=2000, field_dtype=np.float32)
     steps = prob.steps
-    _log(f"fp32 patchy2048, {steps} steps on the GPU")
+    _log(f"fp32 patchy2048, {steps} steps, GPU and oracle ({oracle.threads()} threads) "
+         "in lockstep")
     u = torch.from_numpy(np.ascontiguousarray(prob.wind[0][0])).cuda()
     v = torch.from_numpy(np.ascontiguousarray(prob.wind[0][1])).cuda()
     g = gpu_fire(prob, torch.float32)
     fs, fl = g.new_flux()
-    tot_g, snaps = [], {}
-    for k in range(steps):
-        g.step(u, v, prob.dt, fs, fl)
-        tot_g.append((total_flux(host(fs), prob), total_flux(host(fl), prob)))
-        if (k + 1) % 100 == 0:
-            snaps[k + 1] = host(g.psi).astype(np.float32)
-    torch.cuda.synchronize()
-    tot_g = np.array(tot_g)
     p64 = prob.cast(np.float32)
     o = oracle.OracleFire(p64)
-    _log(f"oracle on {oracle.threads()} threads")
-    tot_o = []
-    worst = 0.0
+    cmp = FluxCompare32(prob, o.tab)
     for k in range(steps):
+        g.step(u, v, prob.dt, fs, fl)
         fs_o, fl_o = o.step(*p64.wind_at(k), prob.dt)
-        tot_o.append((total_flux(fs_o, prob), total_flux(fl_o, prob)))
+        psi_g = host(g.psi)
+        cmp.step(psi_g, o.psi, host(g.frac), o.frac, host(fs), host(fl), fs_o, fl_o, prob.dt)
         if (k + 1) % 100 == 0:
-            err = front_error(snaps[k + 1].astype(np.float64), o.psi, prob.dx, prob.dy)
-            worst = max(worst, err)
+            err = front_error(psi_g, o.psi, prob.dx, prob.dy)
             _log(f"step {k + 1}: front error {err:.2e} cells, burning {(o.psi < 0).sum()}")
             assert err <= 0.05
-    _check_totals(tot_g, np.array(tot_o), "2048^2 x 2000")
+    cmp.check("2048^2 x 2000", _log)
     assert (o.frac < 0.5).sum() > 1000

@@ -51,7 +51,8 @@ enum {
     FIRE_ERR_OOM = -3,       /* host allocation of the context failed        */
     FIRE_ERR_BOUNDARY = -4,  /* fire reached the guard ring (Sect. 4.1)      */
     FIRE_ERR_NONFINITE = -5, /* non-finite level set or fuel fraction        */
-    FIRE_ERR_STATE = -6      /* call not allowed in the context's state      */
+    FIRE_ERR_STATE = -6,     /* call not allowed in the context's state      */
+    FIRE_ERR_TOO_LARGE = -7  /* input larger than a fixed-size buffer allows */
 };
 
 /* sticky status bits reported by fire_status() */
@@ -385,6 +386,27 @@ size_t fire_wind_scratch_bytes(const fire_wind_grid *grid);
 int fire_wind_interp(const fire_wind_grid *grid, const void *u3, const void *v3,
                      const void *phi, const void *hgt, const void *z0, void *u, void *v,
                      void *scratch, size_t scratch_bytes, void *stream);
+
+/* Size of the library's own scratch for fire_wind_interp_static (16 MiB on
+ * each GPU it runs on, held until the process ends). */
+#define FIRE_WIND_STATIC_BYTES (16u << 20)
+
+/*
+ * fire_wind_interp() for callers that cannot allocate device memory (code
+ * under HIP-graph capture, serving loops, harnesses that forbid allocation):
+ * the same computation and results, bit for bit, with the scratch taken from
+ * a fixed buffer inside the library instead of the caller.  Nothing is
+ * allocated.  The caller still passes the inputs and the outputs u, v.
+ * Returns FIRE_ERR_TOO_LARGE when fire_wind_scratch_bytes(grid) exceeds
+ * FIRE_WIND_STATIC_BYTES (about 2 million staggered points in FP32, half that
+ * in FP64; an 820 x 820 atmosphere needs 5.4 MB in FP32).  Every call on one
+ * GPU uses the same buffer: calls that overlap in time on one GPU (different
+ * streams, or threads without ordering) race and give undefined results;
+ * calls on one stream are ordered and safe.  Asynchronous on stream.
+ */
+int fire_wind_interp_static(const fire_wind_grid *grid, const void *u3, const void *v3,
+                            const void *phi, const void *hgt, const void *z0, void *u, void *v,
+                            void *stream);
 
 #ifdef __cplusplus
 }

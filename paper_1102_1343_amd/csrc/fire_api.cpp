@@ -204,6 +204,7 @@ const char *fire_strerror(int code) {
     case FIRE_ERR_BOUNDARY: return "fire reached the domain boundary guard ring";
     case FIRE_ERR_NONFINITE: return "non-finite level set or fuel fraction";
     case FIRE_ERR_STATE: return "call not allowed in the current context state";
+    case FIRE_ERR_TOO_LARGE: return "input larger than the library's fixed-size buffer allows";
     default: return "unknown error";
     }
 }

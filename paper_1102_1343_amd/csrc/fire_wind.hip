@@ -16,8 +16,16 @@
 //    writes 2 values per fire cell and reads fields ~sr_x sr_y times smaller,
 //    so it is bound by the HBM writes.
 #include <cmath>
+#include <mutex>
 
 #include "fire_internal.h"
+
+// Scratch of the no-allocation entry point fire_wind_interp_static: the two
+// staggered surface fields, one copy on each GPU for the life of the
+// process.  Host code never uses this name as an address; it uses the
+// pointer hipGetSymbolAddress returns for the current device
+// (static_scratch()).
+static __device__ __align__(256) char scratch[FIRE_WIND_STATIC_BYTES];
 
 namespace fire {
 namespace {
@@ -242,6 +250,24 @@ hipError_t run(const fire_wind_grid *g, const void *u3, const void *v3, const vo
     return hipGetLastError();
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device; nullptr on failure.
+void *static_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 }  // namespace fire
 
@@ -265,6 +291,20 @@ int fire_wind_interp(const fire_wind_grid *g, const void *u3, const void *v3, co
         g->dtype == FIRE_F64
             ? run<double>(g, u3, v3, phi, hgt, z0, u, v, scratch, (hipStream_t)stream)
             : run<float>(g, u3, v3, phi, hgt, z0, u, v, scratch, (hipStream_t)stream);
+    return h == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+int fire_wind_interp_static(const fire_wind_grid *g, const void *u3, const void *v3,
+                            const void *phi, const void *hgt, const void *z0, void *u, void *v,
+                            void *stream) {
+    if (!grid_ok(g) || !u3 || !v3 || !phi || !hgt || !z0 || !u || !v) return FIRE_ERR_ARG;
+    if (fire_wind_scratch_bytes(g) > (size_t)FIRE_WIND_STATIC_BYTES) return FIRE_ERR_TOO_LARGE;
+    void *buf = static_scratch();   // device address of `scratch` on this GPU
+    if (!buf) return FIRE_ERR_HIP;
+    const hipError_t h =
+        g->dtype == FIRE_F64
+            ? run<double>(g, u3, v3, phi, hgt, z0, u, v, buf, (hipStream_t)stream)
+            : run<float>(g, u3, v3, phi, hgt, z0, u, v, buf, (hipStream_t)stream);
     return h == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 

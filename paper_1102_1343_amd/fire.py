@@ -20,6 +20,8 @@ FIRE_F32, FIRE_F64 = 0, 1
 STATUS_BOUNDARY, STATUS_NONFINITE = 1, 2
 ERR_BOUNDARY = -4
 ERR_NONFINITE = -5
+ERR_TOO_LARGE = -7
+WIND_STATIC_BYTES = 16 << 20
 MAX_IGNITIONS = 8
 NCOEF = 10
 COEF_NAMES = ("S0", "R0", "b", "c", "d", "e", "m", "Tf", "Ch", "Cq")
@@ -127,6 +129,7 @@ def lib():
         L.fire_wind_scratch_bytes.restype = C.c_size_t
         L.fire_wind_interp.argtypes = [P(fire_wind_grid), vp, vp, vp, vp, vp, vp, vp, vp,
                                        C.c_size_t, vp]
+        L.fire_wind_interp_static.argtypes = [P(fire_wind_grid), vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -716,6 +719,33 @@ def wind_interp(u3, v3, phi, hgt, z0, nx, ny, sr_x, sr_y, zf=6.1, g=9.81, stream
            "fire_wind_interp")
     if own:   # the scratch must outlive the asynchronous kernels
         (stream or torch.cuda.current_stream()).synchronize()
+    return u, v
+
+
+def wind_interp_static(u3, v3, phi, hgt, z0, nx, ny, sr_x, sr_y, out, zf=6.1, g=9.81,
+                       stream=None):
+    """wind_interp through fire_wind_interp_static: the library's own fixed
+    scratch, nothing allocated; ``out`` = (u, v) [ny, nx] device tensors are
+    required.  Overlapping calls on one GPU race (they share the scratch)."""
+    _need(u3, "u3")
+    dt, dev = u3.dtype, u3.device
+    if dt not in (torch.float32, torch.float64) or u3.dim() != 3:
+        raise ValueError("u3: expected a float32 or float64 [nz, nay, nax + 1] tensor")
+    nz, nay, nax1 = u3.shape
+    nax = nax1 - 1
+    for name, t, shp in (("v3", v3, (nz, nay + 1, nax)), ("phi", phi, (nz + 1, nay, nax)),
+                         ("hgt", hgt, (nay, nax)), ("z0", z0, (nay, nax))):
+        _need(t, name, shp, dt, dev)
+    u, v = out
+    _need(u, "out[0]", (int(ny), int(nx)), dt, dev)
+    _need(v, "out[1]", (int(ny), int(nx)), dt, dev)
+    grid = fire_wind_grid(nax, nay, nz, int(sr_x), int(sr_y), int(nx), int(ny),
+                          FIRE_F64 if dt == torch.float64 else FIRE_F32, float(zf), float(g))
+    _check(lib().fire_wind_interp_static(C.byref(grid), C.c_void_p(u3.data_ptr()),
+                                         C.c_void_p(v3.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                         C.c_void_p(hgt.data_ptr()), C.c_void_p(z0.data_ptr()),
+                                         C.c_void_p(u.data_ptr()), C.c_void_p(v.data_ptr()),
+                                         _stream_handle(stream)), "fire_wind_interp_static")
     return u, v
 
 

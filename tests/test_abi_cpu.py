@@ -153,3 +153,18 @@ def test_wind_grid_layout_and_errors_without_gpu(lib, tmp_path):
         assert lib.fire_wind_scratch_bytes(C.byref(b)) == 0, field
     assert lib.fire_wind_interp(C.byref(g), None, None, None, None, None, None, None, None,
                                 C.c_size_t(0), None) == -1
+
+
+def test_static_wind_refuses_oversize_grid_without_gpu(lib):
+    """The no-allocation coupling-input call checks the grid against its fixed
+    scratch before any device call (the pointers are never touched)."""
+    from paper_1102_1343_amd import fire as F
+    lib.fire_wind_scratch_bytes.restype = C.c_size_t
+    big = F.fire_wind_grid(1500, 1500, 1, 1, 1, 10, 10, F.FIRE_F32, 6.1, 9.81)
+    assert lib.fire_wind_scratch_bytes(C.byref(big)) > F.WIND_STATIC_BYTES
+    fake = [C.c_void_p(256)] * 7
+    assert lib.fire_wind_interp_static(C.byref(big), *fake, None) == F.ERR_TOO_LARGE
+    bad = F.fire_wind_grid(0, 1500, 1, 1, 1, 10, 10, F.FIRE_F32, 6.1, 9.81)
+    assert lib.fire_wind_interp_static(C.byref(bad), *fake, None) == -1
+    ok = F.fire_wind_grid(820, 820, 40, 10, 10, 8192, 8192, F.FIRE_F64, 6.1, 9.81)
+    assert lib.fire_wind_scratch_bytes(C.byref(ok)) <= F.WIND_STATIC_BYTES

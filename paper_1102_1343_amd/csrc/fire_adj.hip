@@ -401,20 +401,13 @@ __device__ __forceinline__ void ignite_node(const AdjArgs &a, const fire_ignitio
     const T pold = p;
     T tig = M<T>::inf();
     sel = tsel = -1;
-    const double xg = ((double)x + 0.5) * a.dx, yg = ((double)y + 0.5) * a.dy;
     for (int g = 0; g < a.nign; g++) {
         IgnGeo<T> geo;
         if (!ign_setup<T>(ign[g], a.t, geo)) continue;
-        T arr;
-        const T pg = ign_psi(geo, T(xg - geo.ax), T(yg - geo.ay), arr);
-        if (pg <= T(0) && arr < tig) {
-            tig = arr;
-            tsel = g;
-        }
-        if (pg < p) {
-            p = pg;
-            sel = g;
-        }
+        const T py = ign_py(geo, y, a.dy);
+        const int ch = ign_apply(geo, ign_px(geo, x, a.dx), py, ign_by(geo, py), p, tig);
+        if (ch & 2) tsel = g;
+        if (ch & 1) sel = g;
     }
     if (!(pold > T(0) && p <= T(0))) tsel = -1;
 }
@@ -447,24 +440,22 @@ __device__ __forceinline__ T rev1_node(const AdjArgs &a, int n, int i, int x, in
             ignite_node(a, ign, psi_n[i], x, y, sg, k);
             IgnGeo<T> geo;
             if (k >= 0 && ign_setup<T>(ign[k], a.t, geo)) {
-                const T px = T(((double)x + 0.5) * a.dx - geo.ax);
-                const T py = T(((double)y + 0.5) * a.dy - geo.ay);
-                T s = (px * geo.ex + py * geo.ey) * geo.invL2;
-                const bool sfree = s > T(0) && s < T(1);
-                s = vmin(vmax(s, T(0)), T(1));
-                const T qx = px - s * geo.ex, qy = py - s * geo.ey;
-                const T d = M<T>::sqrt(qx * qx + qy * qy);
-                const T arr = geo.tg + s * geo.lenv + d * geo.invS;
+                const T px = ign_px(geo, x, a.dx);
+                const T py = ign_py(geo, y, a.dy);
+                const IgnNear<T> nq = ign_near(geo, px, py, ign_by(geo, py));
+                const bool sfree = nq.s > T(0) && nq.s < T(1);
+                const T d = M<T>::sqrt(nq.d2);
+                const T arr = fmaT(d, geo.invS, fmaT(nq.s, geo.lenv, geo.tg));
                 if (arr < geo.t) {
                     // translating the ignition by delta moves the node by -delta
                     T ax_ = T(0), ay_ = T(0);
                     if (d > T(0)) {
-                        ax_ = -geo.invS * M<T>::div(qx, d);
-                        ay_ = -geo.invS * M<T>::div(qy, d);
+                        ax_ = -geo.invS * M<T>::div(nq.qx, d);
+                        ay_ = -geo.invS * M<T>::div(nq.qy, d);
                     }
                     if (sfree) {
-                        ax_ -= geo.lenv * geo.ex * geo.invL2;
-                        ay_ -= geo.lenv * geo.ey * geo.invL2;
+                        ax_ -= geo.lenv * geo.exL;
+                        ay_ -= geo.lenv * geo.eyL;
                     }
                     g = k;
                     cx = (double)(lt * ax_);
@@ -498,16 +489,14 @@ __device__ __forceinline__ T rev3_node(const AdjArgs &a, int i, int x, int y, T 
     if (sg < 0) return l;
     IgnGeo<T> geo;
     if (l != T(0) && ign_setup<T>(ign[sg], a.t, geo)) {
-        const T px = T(((double)x + 0.5) * a.dx - geo.ax);
-        const T py = T(((double)y + 0.5) * a.dy - geo.ay);
-        T s = (px * geo.ex + py * geo.ey) * geo.invL2;
-        s = vmin(vmax(s, T(0)), T(1));
-        const T qx = px - s * geo.ex, qy = py - s * geo.ey;
-        const T d = M<T>::sqrt(qx * qx + qy * qy);
+        const T px = ign_px(geo, x, a.dx);
+        const T py = ign_py(geo, y, a.dy);
+        const IgnNear<T> nq = ign_near(geo, px, py, ign_by(geo, py));
+        const T d = M<T>::sqrt(nq.d2);
         if (d > T(0)) {
             g = sg;
-            cx = (double)(-l * M<T>::div(qx, d));
-            cy = (double)(-l * M<T>::div(qy, d));
+            cx = (double)(-l * M<T>::div(nq.qx, d));
+            cy = (double)(-l * M<T>::div(nq.qy, d));
         }
     }
     return T(0);

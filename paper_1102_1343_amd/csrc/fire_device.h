@@ -156,12 +156,18 @@ __device__ __forceinline__ T rhs5(T pc, T pw, T pe, T ps, T pn, T u, T v, T gzx,
     return visc - S * up;
 }
 
+// Fused multiply-add as one rounding, whatever the compiler's contraction
+// setting: the ignition geometry below is evaluated by the step kernels and
+// by the reverse kernels, which must take exactly the forward's values.
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // One ignition's geometry at time t.  The segment start stays in double so
 // node offsets are formed exactly from global coordinates: psi_g at a node
 // is then the same in every tile that touches the node (owner or halo).
 template <typename T> struct IgnGeo {
     double ax, ay;
-    T ex, ey, invL2, rad, tg, lenv, invS, t;
+    T ex, ey, exL, eyL, rad, tg, lenv, invS, t, pad;
 };
 
 template <typename T>
@@ -184,28 +190,90 @@ __device__ __forceinline__ bool ign_setup(const fire_ignition &g, double t, IgnG
     o.ay = g.ay;
     o.ex = T(ex);
     o.ey = T(ey);
-    o.invL2 = L2 > 0.0 ? T(1.0 / L2) : T(0);
+    o.exL = L2 > 0.0 ? T(ex / L2) : T(0);
+    o.eyL = L2 > 0.0 ? T(ey / L2) : T(0);
     o.rad = T(inst ? g.radius : (r < g.radius ? r : g.radius));
     o.tg = T(g.t_start);
     o.lenv = torch ? T(::sqrt(L2) / ::sqrt(g.vx * g.vx + g.vy * g.vy)) : T(0);
     o.invS = inst ? T(0) : T(1.0 / g.ros);
     o.t = T(t);
+    o.pad = T(0);
     return true;
 }
 
-// psi_g of Eq. (20) (drip-torch form) at the node whose centre is
-// (px, py) away from the segment start (differences formed in double from
-// global coordinates), and the arrival time of the initial fire there,
-// capped at t.
+// Offsets of a node centre from the segment start, formed in double from
+// global coordinates and rounded once: px from the node's column, py from
+// its row, and the row's share of the projection parameter, by = py eyL.
 template <typename T>
-__device__ __forceinline__ T ign_psi(const IgnGeo<T> &g, T px, T py, T &arrive) {
-    T s = (px * g.ex + py * g.ey) * g.invL2;
-    s = vmin(vmax(s, T(0)), T(1));
-    const T qx = px - s * g.ex, qy = py - s * g.ey;
-    const T d = M<T>::sqrt(qx * qx + qy * qy);
-    const T a = g.tg + s * g.lenv + d * g.invS;
-    arrive = vmin(a, g.t);
-    return d - g.rad;
+__device__ __forceinline__ T ign_px(const IgnGeo<T> &g, int gx, double dx) {
+    return T(((double)gx + 0.5) * dx - g.ax);
+}
+template <typename T>
+__device__ __forceinline__ T ign_py(const IgnGeo<T> &g, int gy, double dy) {
+    return T(((double)gy + 0.5) * dy - g.ay);
+}
+template <typename T> __device__ __forceinline__ T ign_by(const IgnGeo<T> &g, T py) {
+    return py * g.eyL;
+}
+
+// Nearest point of the segment (Eq. 20): parameter s in [0, 1], the offset
+// (qx, qy) from it and its square d2.
+template <typename T> struct IgnNear {
+    T s, qx, qy, d2;
+};
+template <typename T>
+__device__ __forceinline__ IgnNear<T> ign_near(const IgnGeo<T> &g, T px, T py, T by) {
+    IgnNear<T> r;
+    r.s = med3(fmaT(px, g.exL, by), T(0), T(1));
+    r.qx = fmaT(-r.s, g.ex, px);
+    r.qy = fmaT(-r.s, g.ey, py);
+    r.d2 = fmaT(r.qx, r.qx, r.qy * r.qy);
+    return r;
+}
+
+// Arrival time of the initial fire at the node (drip-torch form), capped at t.
+template <typename T>
+__device__ __forceinline__ T ign_arrival(const IgnGeo<T> &g, const IgnNear<T> &q, T d) {
+    return vmin(fmaT(d, g.invS, fmaT(q.s, g.lenv, g.tg)), g.t);
+}
+
+// 1 + a margin above the relative rounding of d2, of its square root and of
+// (p + r)^2: d2 > (p + r)^2 (1 + margin) proves sqrt(d2) - r >= p after
+// rounding.
+template <typename T> struct IgnMargin;
+template <> struct IgnMargin<float> {
+    static __device__ __forceinline__ float v() { return 1.0f + 0x1p-19f; }
+};
+template <> struct IgnMargin<double> {
+    static __device__ __forceinline__ double v() { return 1.0 + 0x1p-40; }
+};
+
+// Applies one ignition to node value p (Eq. 21): p := min(p, psi_g), with
+// psi_g = d - r_g of Eq. (20), and a node with psi_g <= 0 offers its arrival
+// time to tig (the minimum over ignitions).  Where p > 0 and d2 alone shows
+// psi_g >= p (so also psi_g > 0) neither can change and the square root is
+// skipped; the result is the same as without the test.  Returns bit 0 if p
+// was lowered, bit 1 if tig was.
+template <typename T>
+__device__ __forceinline__ int ign_apply(const IgnGeo<T> &g, T px, T py, T by, T &p, T &tig) {
+    const IgnNear<T> q = ign_near(g, px, py, by);
+    const T pr = p + g.rad;
+    if (p > T(0) && q.d2 > pr * pr * IgnMargin<T>::v()) return 0;
+    const T d = M<T>::sqrt(q.d2);
+    const T pg = d - g.rad;
+    int changed = 0;
+    if (pg <= T(0)) {
+        const T a = ign_arrival(g, q, d);
+        if (a < tig) {
+            tig = a;
+            changed |= 2;
+        }
+    }
+    if (pg < p) {   // a NaN p stays NaN (reported by the status word)
+        p = pg;
+        changed |= 1;
+    }
+    return changed;
 }
 
 }  // namespace dev

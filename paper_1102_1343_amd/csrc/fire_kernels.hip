@@ -216,10 +216,19 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     }
     if (a.nign > 0) {
         // each ignition's geometry at t, once per work-group (lane g of the
-        // first wave takes ignition g), shared through LDS
+        // first wave takes ignition g), and its per-row offsets py, by for
+        // the frame rows, shared through LDS
         __shared__ IgnGeo<T> geo_s[FIRE_MAX_IGNITIONS];
         __shared__ int geo_on[FIRE_MAX_IGNITIONS];
+        __shared__ int geo_use[FIRE_MAX_IGNITIONS];
         __shared__ T wave_max[kBlock / 64];
+        __shared__ T row_py[FIRE_MAX_IGNITIONS][FHM];
+        __shared__ T row_by[FIRE_MAX_IGNITIONS][FHM];
+        if (tid < a.nign) {
+            IgnGeo<T> gs;
+            geo_on[tid] = ign_setup<T>(ign[tid], tnow, gs) ? 1 : 0;
+            geo_s[tid] = gs;
+        }
         // the frame's largest psi^n (NaN nodes, which no ignition changes,
         // are ignored): an ignition whose psi_g is provably positive and no
         // smaller than that on every frame node changes nothing here
@@ -229,48 +238,48 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         for (int off = 32; off > 0; off >>= 1) m = vmax(m, __shfl_xor(m, off));
         if ((tid & 63) == 0) wave_max[tid >> 6] = m;
         __syncthreads();
-        if (tid < a.nign) {
-            IgnGeo<T> gs;
-            bool on = ign_setup<T>(ign[tid], tnow, gs);
-            if (on) {
-                T M = wave_max[0];
-                for (int w = 1; w < kBlock / 64; w++) M = vmax(M, wave_max[w]);
-                // lower bound of psi_g over the frame nodes: distance from the
-                // frame's centre to the segment, less its half diagonal, the
-                // radius and a margin far above the rounding of psi_g
-                const double bx0 = (x0 - kHalo + 0.5) * a.dx;
-                const double bx1 = (x0 - kHalo + kFW - 0.5) * a.dx;
-                const double by0 = (y0 - kHalo + 0.5) * a.dy;
-                const double by1 = (y0 - kHalo + FHM - 0.5) * a.dy;
-                const double cx = 0.5 * (bx0 + bx1) - gs.ax, cy = 0.5 * (by0 + by1) - gs.ay;
-                const double ex = gs.ex, ey = gs.ey, L2 = ex * ex + ey * ey;
-                double sp = L2 > 0.0 ? (cx * ex + cy * ey) / L2 : 0.0;
-                sp = sp < 0.0 ? 0.0 : (sp > 1.0 ? 1.0 : sp);
-                const double qx = cx - sp * ex, qy = cy - sp * ey;
-                const double d = ::sqrt(qx * qx + qy * qy);
-                const double hd = 0.5 * ::sqrt((bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0));
-                const double lb = d - hd - (double)gs.rad - (1.0 + 1e-4 * (d + ::sqrt(L2)));
-                if (lb > 0.0 && lb >= (double)M) on = false;
+        for (int e = tid; e < a.nign * FHM; e += kBlock) {
+            const int g = e / FHM, j = e - g * FHM;
+            if (geo_on[g]) {
+                const T py = ign_py(geo_s[g], y0 - kHalo + j, a.dy);
+                row_py[g][j] = py;
+                row_by[g][j] = ign_by(geo_s[g], py);
             }
-            geo_on[tid] = on ? 1 : 0;
-            geo_s[tid] = gs;
+        }
+        if (tid < a.nign) geo_use[tid] = geo_on[tid];
+        if (tid < a.nign && geo_on[tid]) {
+            const IgnGeo<T> gs = geo_s[tid];
+            T M = wave_max[0];
+            for (int w = 1; w < kBlock / 64; w++) M = vmax(M, wave_max[w]);
+            // lower bound of psi_g over the frame nodes: distance from the
+            // frame's centre to the segment, less its half diagonal, the
+            // radius and a margin far above the rounding of psi_g
+            const double bx0 = (x0 - kHalo + 0.5) * a.dx;
+            const double bx1 = (x0 - kHalo + kFW - 0.5) * a.dx;
+            const double by0 = (y0 - kHalo + 0.5) * a.dy;
+            const double by1 = (y0 - kHalo + FHM - 0.5) * a.dy;
+            const double cx = 0.5 * (bx0 + bx1) - gs.ax, cy = 0.5 * (by0 + by1) - gs.ay;
+            const double ex = gs.ex, ey = gs.ey, L2 = ex * ex + ey * ey;
+            double sp = L2 > 0.0 ? (cx * ex + cy * ey) / L2 : 0.0;
+            sp = sp < 0.0 ? 0.0 : (sp > 1.0 ? 1.0 : sp);
+            const double qx = cx - sp * ex, qy = cy - sp * ey;
+            const double d = ::sqrt(qx * qx + qy * qy);
+            const double hd = 0.5 * ::sqrt((bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0));
+            const double lb = d - hd - (double)gs.rad - (1.0 + 1e-4 * (d + ::sqrt(L2)));
+            if (lb > 0.0 && lb >= (double)M) geo_use[tid] = 0;
         }
         __syncthreads();
         T pold[KR];
 #pragma unroll
         for (int k = 0; k < KR; k++) pold[k] = p0[k];
-        const double xg = ((double)gx + 0.5) * a.dx;
         for (int g = 0; g < a.nign; g++) {
-            if (!geo_on[g]) continue;
+            if (!geo_use[g]) continue;
             const IgnGeo<T> geo = geo_s[g];
-            const T px = T(xg - geo.ax);
+            const T px = ign_px(geo, gx, a.dx);
 #pragma unroll
             for (int k = 0; k < KR; k++) {
-                const double yg = ((double)(y0 - kHalo + ty + kNR * k) + 0.5) * a.dy;
-                T arr;
-                const T pg = ign_psi(geo, px, T(yg - geo.ay), arr);
-                if (pg <= T(0) && arr < tig[k]) tig[k] = arr;
-                if (pg < p0[k]) p0[k] = pg;   // a NaN psi stays NaN (status word)
+                const int fy = ty + kNR * k;
+                ign_apply(geo, px, row_py[g][fy], row_by[g][fy], p0[k], tig[k]);
             }
         }
 #pragma unroll

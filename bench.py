@@ -400,13 +400,13 @@ def run_adjoint(args, prob, pert, dtype):
     log(f"{K} steps: plain forward {fwd_ms:.1f} ms, recording forward {rec_ms:.1f} ms, "
         f"backward {bwd_ms:.1f} ms; loss {loss:.4e}; F_end equal to the plain run: {same}")
     out = {
-        "metric": "adjoint/forward cost",
-        "value": bwd_ms / fwd_ms,
+        "metric": "gradient cost: (recording forward + backward) / plain forward",
+        "value": (rec_ms + bwd_ms) / fwd_ms,
         "unit": "x",
         "n_gpus": 1,
         "steps": K,
         "warmup": 1,
-        "ms_per_step": bwd_ms / K,
+        "ms_per_step": (rec_ms + bwd_ms) / K,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -419,7 +419,7 @@ def run_adjoint(args, prob, pert, dtype):
                    "nx": prob.nx, "ny": prob.ny, "every": args.every},
         "adjoint": {"forward_ms": fwd_ms, "recording_forward_ms": rec_ms, "backward_ms": bwd_ms,
                     "backward_reps": BWD_REPS, "backward_repeats_bit_equal": repeat_equal,
-                    "forward_and_backward_over_forward": (rec_ms + bwd_ms) / fwd_ms,
+                    "backward_over_forward": bwd_ms / fwd_ms,
                     "loss": loss, "F_end_equals_plain_run": same,
                     "grad_norms": {"u": float(gu.double().norm()), "v": float(gv.double().norm()),
                                    "mult": float(np.linalg.norm(gm)),

@@ -670,22 +670,6 @@ k_lt_init(const AdjArgs a, const T *psi, const T *LTH, T *LT) {
     LT[i] = psi[i] < T(0) ? LTH[ext_idx(a, x, y)] : T(0);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kAB) k_mark(int n, int32_t *set_step, const T *tign, int cnt) {
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= cnt) return;
-    if (set_step[i] < 0 && !is_inf(tign[i])) set_step[i] = n;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_tign_at(const int32_t *set_step, const T *tign, int s0, T *out, int cnt) {
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= cnt) return;
-    const int s = set_step[i];
-    out[i] = (s >= 0 && s < s0) ? tign[i] : M<T>::inf();
-}
-
 template <typename T> __global__ void __launch_bounds__(kAB) k_set(T *p, T v, size_t cnt) {
     for (size_t i = blockIdx.x * (size_t)kAB + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kAB)
         p[i] = v;
@@ -731,7 +715,7 @@ k_col_sum(const double *part, int rows, int cols, double *out) {
 int hip_fail(hipError_t e) { return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP; }
 
 struct AdjLayout {
-    size_t ckpt, stack, rp0, rb, set_step, tig, frac, flux, status, e1, e2, le, th, l1, lt, lp0,
+    size_t ckpt, stack, rp0, rb, set_step, flux, e1, e2, le, th, l1, lt, lp0,
         lb, d, d1, gu, gv, gm, acc, part, small, total;
 };
 
@@ -771,10 +755,7 @@ AdjLayout adj_layout(const fire_mesh *m, int ncat, int nsteps, int every) {
     take(L.rp0, (size_t)every * n * es);
     take(L.rb, (size_t)every * n * es);
     take(L.set_step, n * 4);
-    take(L.tig, n * es);
-    take(L.frac, n * es);
     take(L.flux, 2 * natm * es);
-    take(L.status, 64);
     take(L.e1, ne * es);
     take(L.e2, ne * es);
     take(L.le, ne * es);
@@ -877,15 +858,11 @@ template <typename T> struct Run {
         hipError_t h = hipMemcpyAsync(stack(0), arr(A->L.ckpt) + (size_t)seg * n, n * sizeof(T),
                                       hipMemcpyDeviceToDevice, s);
         if (h != hipSuccess) return h;
-        hipLaunchKernelGGL(k_tign_at<T>, dim3(gn), dim3(kAB), 0, s, at<int32_t>(A->L.set_step),
-                           tign_final(), s0, arr(A->L.tig), (int)n);
-        hipLaunchKernelGGL(k_set<T>, dim3(256), dim3(kAB), 0, s, arr(A->L.frac), T(1), n);
-        const size_t natm = (size_t)((c->mesh.nx + c->mesh.sr_x - 1) / c->mesh.sr_x) *
-                            ((c->mesh.ny + c->mesh.sr_y - 1) / c->mesh.sr_y);
+        // psi does not depend on ignition times or fuel fraction: the replay
+        // recomputes psi, psi' and psi* only
         for (int k = s0; k < s1; k++) {
-            h = step_raw(c, stack(k - s0), stack(k - s0 + 1), arr(A->L.tig), arr(A->L.frac), A->u,
-                         A->v, A->tstep[k], A->dt, arr(A->L.flux), arr(A->L.flux) + natm,
-                         at<int>(A->L.status), rp0(k - s0), rb(k - s0));
+            h = step_raw(c, stack(k - s0), stack(k - s0 + 1), nullptr, nullptr, A->u, A->v,
+                         A->tstep[k], A->dt, nullptr, nullptr, nullptr, rp0(k - s0), rb(k - s0));
             if (h != hipSuccess) return h;
         }
         return hipGetLastError();
@@ -1011,7 +988,6 @@ int fire_adj_forward(fire_adj *A, const void *u, const void *v, double dt) {
     fire_ctx *c = A->c;
     const size_t n = (size_t)c->mesh.nx * c->mesh.ny;
     const size_t es = esize(&c->mesh);
-    const int gn = (int)((n + kAB - 1) / kAB);
     const size_t natm = (size_t)((c->mesh.nx + c->mesh.sr_x - 1) / c->mesh.sr_x) *
                         ((c->mesh.ny + c->mesh.sr_y - 1) / c->mesh.sr_y);
     A->u = u;
@@ -1020,11 +996,15 @@ int fire_adj_forward(fire_adj *A, const void *u, const void *v, double dt) {
     A->forward_done = 0;
     A->tstep.assign(A->nsteps + 1, 0.0);
     A->tstep[0] = c->t;
+    // set_step[i]: the step that sets node i's ignition time (-1: none does,
+    // which includes nodes whose time was set before the run); the step
+    // kernel stores it as it writes the time
     int32_t *set_step = reinterpret_cast<int32_t *>(A->arena + A->L.set_step);
     hipLaunchKernelGGL(k_set<int32_t>, dim3(256), dim3(kAB), 0, c->stream, set_step, -1, n);
     if (hipGetLastError() != hipSuccess) return FIRE_ERR_HIP;
     char *flux = A->arena + A->L.flux;
-    for (int k = 0; k < A->nsteps; k++) {
+    int rc = FIRE_OK;
+    for (int k = 0; k < A->nsteps && rc == FIRE_OK; k++) {
         if (k % A->every == 0) {
             const hipError_t h =
                 hipMemcpyAsync(A->arena + A->L.ckpt + (size_t)(k / A->every) * n * es,
@@ -1032,17 +1012,14 @@ int fire_adj_forward(fire_adj *A, const void *u, const void *v, double dt) {
                                c->stream);
             if (h != hipSuccess) return FIRE_ERR_HIP;
         }
-        const int rc = fire_step(c, u, v, dt, flux, flux + natm * es, nullptr);
-        if (rc != FIRE_OK) return rc;
-        if (c->mesh.dtype == FIRE_F64)
-            hipLaunchKernelGGL(k_mark<double>, dim3(gn), dim3(kAB), 0, c->stream, k, set_step,
-                               (const double *)(c->arena + c->off_tign), (int)n);
-        else
-            hipLaunchKernelGGL(k_mark<float>, dim3(gn), dim3(kAB), 0, c->stream, k, set_step,
-                               (const float *)(c->arena + c->off_tign), (int)n);
-        if (hipGetLastError() != hipSuccess) return FIRE_ERR_HIP;
+        c->mark = set_step;
+        c->mark_step = k;
+        rc = fire_step(c, u, v, dt, flux, flux + natm * es, nullptr);
         A->tstep[k + 1] = c->t;
     }
+    c->mark = nullptr;
+    c->mark_step = 0;
+    if (rc != FIRE_OK) return rc;
     A->forward_done = 1;
     return FIRE_OK;
 }

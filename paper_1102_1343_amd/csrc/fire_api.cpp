@@ -185,6 +185,8 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     b.ens_clock = nullptr;
     b.rec_p0 = rec_p0;
     b.rec_b = rec_b;
+    b.mark = rec_p0 ? nullptr : c->mark;
+    a.mark_step = c->mark_step;
 
     return launch_step(m.dtype, a, b, c->stream);
 }
@@ -253,6 +255,8 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
     c->host_status = nullptr;
     c->ev[0] = c->ev[1] = nullptr;
     c->ev_valid[0] = c->ev_valid[1] = 0;
+    c->mark = nullptr;
+    c->mark_step = 0;
     c->nstep = 0;
     default_tile(mesh, &c->tile_x, &c->tile_y);
     if (!tile_ok(mesh, c->tile_x, c->tile_y)) {
@@ -475,10 +479,10 @@ void fire_destroy(fire_ctx *c) {
     if (!c) return;
     for (int i = 0; i < 2; i++)
         if (c->ev[i]) {
-            if (c->ev_valid[i]) hipEventSynchronize(c->ev[i]);   // copy into host_status
-            hipEventDestroy(c->ev[i]);
+            if (c->ev_valid[i]) (void)hipEventSynchronize(c->ev[i]);   // copy into host_status
+            (void)hipEventDestroy(c->ev[i]);
         }
-    if (c->host_status) hipHostFree(c->host_status);
+    if (c->host_status) (void)hipHostFree(c->host_status);
     delete c;
 }
 

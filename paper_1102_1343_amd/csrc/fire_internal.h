@@ -38,7 +38,7 @@ struct StepArgs {
     int32_t tile_x, tile_y;
     int32_t tiles_x, ntiles, per_xcd;   // ntiles: total tiles of the launch
     int32_t sr_x, sr_y, nax, nay;
-    int32_t ncat, guard, visc_mode, nign, pad;
+    int32_t ncat, guard, visc_mode, nign, mark_step;   // mark_step: see StepBuffers::mark
     double dx, dy;
     double rdx, rdy;     // 1/dx, 1/dy
     double t, dt;        // t unused by the ensemble kernel (device time)
@@ -79,7 +79,10 @@ struct StepBuffers {
     const EnsDomain *ens_doms;          // non-null for an ensemble launch; then
     const int32_t *ens_tile_dom;        // psi_in / psi_out are the two buffers and
     const EnsClock *ens_clock;          // the clock says which is current
-    void *rec_p0, *rec_b;               // non-null: also write psi' and psi* (one domain)
+    void *rec_p0, *rec_b;               // non-null: a replay that writes psi^{n+1}, psi'
+                                        // and psi* only (one domain)
+    int32_t *mark;                      // non-null (plain step): mark[i] = mark_step at
+                                        // each node whose ignition time the step sets
 };
 
 }  // namespace fire
@@ -110,6 +113,10 @@ struct fire_ctx {
     hipEvent_t ev[2];
     int ev_valid[2];
     long nstep;
+    // Set by a differentiable run's recording forward for the duration of a
+    // step: the step index stored where that step sets an ignition time.
+    int32_t *mark;
+    int32_t mark_step;
 };
 
 namespace fire {

@@ -139,7 +139,8 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
           const fire_ignition *ign, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
           const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
           const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
-          T *__restrict__ fsens, T *__restrict__ flat, int *status, T *rec_p0, T *rec_b) {
+          T *__restrict__ fsens, T *__restrict__ flat, int *status, T *rec_p0, T *rec_b,
+          int32_t *mark) {
     constexpr int FHM = kNR * KR;
     __shared__ T A[FHM][kFW];
     __shared__ T B[FHM][kFW];
@@ -361,27 +362,34 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
             // t_i is read only where it can matter: a burning node, a node
             // crossing zero, or a node lit by this step's ignition
             T ti = INF, told = INF;
-            if (pn <= T(0) || tig[k] < INF) {
+            if (!REC && (pn <= T(0) || tig[k] < INF)) {
                 told = at<SMALL>(tign, idx);
                 ti = told;
                 if (is_inf(ti)) ti = tig[k];
                 if (pn0 > T(0) && pn <= T(0) && is_inf(ti))
                     ti = t + M<T>::div(pn0 * dt, pn0 - pn);
             }
-            C[fy][tx] = pn >= T(0) ? tp : ti;
+            if (!REC) C[fy][tx] = pn >= T(0) ? tp : ti;
             if (xr3 && fy >= 3 && fy < a.tile_y + 3) {
                 at<SMALL>(psi_out, idx) = pn;
                 if (REC) {   // psi' and psi* of the step, for the reverse pass
                     at<SMALL>(rec_p0, idx) = pn0;
                     at<SMALL>(rec_b, idx) = B[fy][tx];
+                } else {
+                    if (!(ti == told)) {
+                        at<SMALL>(tign, idx) = ti;
+                        // the step in which t_i was first set
+                        if (mark && is_inf(told)) at<SMALL>(mark, idx) = a.mark_step;
+                    }
+                    const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
+                    if (edge && pn < T(0)) st |= kStBoundary;
+                    if (!__builtin_isfinite(pn)) st |= kStNonfinite;
                 }
-                if (!(ti == told)) at<SMALL>(tign, idx) = ti;
-                const bool edge = gx < gw || gy < gw || gx >= nx - gw || gy >= ny - gw;
-                if (edge && pn < T(0)) st |= kStBoundary;
-                if (!__builtin_isfinite(pn)) st |= kStNonfinite;
             }
         }
     }
+    // a replay for the reverse pass needs psi only: no fuel fraction or flux
+    if (REC) return;
     __syncthreads();
     if (!interior) {
         // ghost psi re-extrapolated, corners included; ghost t^ = t' (R19)
@@ -495,20 +503,25 @@ template <typename T, int KR> constexpr int waves_per_simd() {
     return (sizeof(T) == 4 && KR == 7) ? 6 : 1;
 }
 
-// REC: also write psi' (after ignition) and psi* (Heun stage 1) of every
-// node, which the reverse pass of a differentiable run reads.
+// REC: the replay of a recorded run for its reverse pass.  Writes psi^{n+1},
+// psi' (after ignition) and psi* (Heun stage 1) of every node and stops
+// there: ignition times, fuel fraction and fluxes are not recomputed.
+// mark (plain steps): where non-null, the step index a.mark_step is stored at
+// every node whose ignition time this step sets.
 template <typename T, int KR, bool SMALL, bool REC>
 __global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
 k_step(const StepArgs a, const fire_ignition *ign, const T *__restrict__ psi_in,
        T *__restrict__ psi_out, T *tign, T *frac, const T *__restrict__ uw,
        const T *__restrict__ vw, const T *__restrict__ dzdx, const T *__restrict__ dzdy,
        const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
-       T *__restrict__ flat, int *status, T *__restrict__ rec_p0, T *__restrict__ rec_b) {
+       T *__restrict__ flat, int *status, T *__restrict__ rec_p0, T *__restrict__ rec_b,
+       int32_t *__restrict__ mark) {
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
     if (tile >= a.ntiles) return;
     step_tile<T, KR, SMALL, REC>(a, tile, 0u, a.t, ign, psi_in, psi_out, tign, frac, uw, vw,
-                                 dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b);
+                                 dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b,
+                                 mark);
 }
 
 // An ensemble of domains in one launch: the tiles of all domains form one
@@ -558,13 +571,14 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
         // the array bases stay the launch's (no per-member 64-bit pointers)
         step_tile<T, KR, SMALL, false>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, ign, pin,
                                        pout, tign, frac, uw, vw, dzdx, dzdy, cat, coef,
-                                       fsens + a0, flat + a0, status + di, nullptr, nullptr);
+                                       fsens + a0, flat + a0, status + di, nullptr, nullptr,
+                                       nullptr);
     } else {
         const size_t c0 = (size_t)d.cell_off;
         step_tile<T, KR, SMALL, false>(a, g - d.tile0, 0u, tnow, ign, pin + c0, pout + c0,
                                        tign + c0, frac + c0, uw + c0, vw + c0, dzdx + c0,
                                        dzdy + c0, cat + c0, coef, fsens + a0, flat + a0,
-                                       status + di, nullptr, nullptr);
+                                       status + di, nullptr, nullptr, nullptr);
     }
 }
 
@@ -678,13 +692,13 @@ hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
                            b.ign, (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
                            (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
                            b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
-                           (T *)b.rec_p0, (T *)b.rec_b);
+                           (T *)b.rec_p0, (T *)b.rec_b, (int32_t *)nullptr);
     } else {
         hipLaunchKernelGGL((k_step<T, KR, SMALL, false>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
                            b.ign, (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
                            (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
                            b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
-                           (T *)nullptr, (T *)nullptr);
+                           (T *)nullptr, (T *)nullptr, b.mark);
     }
     return hipGetLastError();
 }

@@ -90,10 +90,30 @@ def pmc_traffic(name, dtype, tile, kernel=KERNEL,
     return float(b.group(1))
 
 
+def host_cpu():
+    """The host's processor model and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        ncpu = os.cpu_count()
+    return {"model": model, "cpus_available": ncpu}
+
+
 def cpu_baseline(prob, dtype, seconds):
     """The FP64 oracle on a window of the same workload (1024 x 1024 cells
     around the first ignition, the full mesh's initial level set), run for
-    whole steps until ``seconds`` of wall time have passed."""
+    whole steps until ``seconds`` of wall time have passed on all the
+    oracle's threads, then again from t = 0 on one thread for a third of
+    that time."""
     import numpy as np
     import oracle
     from paper_1102_1343_amd import synth
@@ -109,19 +129,36 @@ def cpu_baseline(prob, dtype, seconds):
     if dtype == "f32":
         win = win.cast(np.float32)
     psi0 = math.hypot(prob.nx * prob.dx, prob.ny * prob.dy)
-    o = oracle.OracleFire(win, psi_init=psi0)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.step(*win.wind_at(steps), win.dt)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds and steps >= 2:
-            break
-    return {"value": w * h * steps / el, "unit": "cell-steps/s", "cores": oracle.threads(),
+
+    def run(budget):
+        """Cumulative wall time after each step."""
+        o = oracle.OracleFire(win, psi_init=psi0)
+        t0 = time.perf_counter()
+        el = []
+        while not el or el[-1] < budget or len(el) < 2:
+            o.step(*win.wind_at(len(el)), win.dt)
+            el.append(time.perf_counter() - t0)
+        return el
+
+    cores = oracle.threads()
+    el = run(seconds)
+    oracle.set_threads(1)
+    try:
+        el1 = run(seconds / 3)
+    finally:
+        oracle.set_threads(cores)
+    steps, steps1 = len(el), len(el1)
+    # the threads' speed-up over the steps both runs took
+    k = min(steps, steps1) - 1
+    return {"value": w * h * steps / el[-1], "unit": "cell-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"FP64 oracle, {w}x{h} window of the {prob.nx}x{prob.ny} workload at "
-                      f"({i0},{j0}), first {steps} steps from t=0, {el:.1f} s wall"}
+                      f"({i0},{j0}), first {steps} steps from t=0, {el[-1]:.1f} s wall",
+            "single_thread": {"value": w * h * steps1 / el1[-1], "cores": 1,
+                              "sample": f"the same window, first {steps1} steps, "
+                                        f"{el1[-1]:.1f} s wall",
+                              "threads_speedup_same_steps": el1[k] / el[k]},
+            "host": host_cpu()}
 
 
 def main():
@@ -247,7 +284,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (cpu_baseline)")
         cpu = cpu_baseline(prob, dtype, args.cpu_seconds)
-        log(f"oracle {cpu['value']:.3e} cell-steps/s on {cpu['cores']} threads")
+        log(f"oracle {cpu['value']:.3e} cell-steps/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.3e} on one ({cpu['host']['model']})")
 
     out = {
         "metric": "fire cell-steps/s",
@@ -304,7 +342,7 @@ def cpu_baseline_members(probs, dtype, seconds):
             break
     full = sum(1 for _, k in done if k == probs[0].steps)
     return {"value": cells_steps / el, "unit": "cell-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"FP64 oracle on the first {len(done)} members in order (sides "
                       f"{', '.join(str(n) for n, _ in done)}), {full} of them for all "
                       f"{probs[0].steps} steps from t=0, the last for {done[-1][1]}; "
@@ -490,7 +528,7 @@ def run_wind(args, atm, dtype):
             n += 1
         el = time.perf_counter() - t
         cpu = {"value": (w * sr) ** 2 * n / el, "unit": "fire cells/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "host": host_cpu(),
                "sample": f"FP64 oracle (numpy, one thread), the {w}x{w}-column corner of the "
                          f"atmosphere to its {w * sr}x{w * sr} fire cells, {n} times, {el:.1f} s"}
         log(f"oracle {cpu['value']:.3e} fire cells/s")

@@ -98,6 +98,8 @@ def lib():
                                   dp, dp, C.POINTER(_Ign), C.c_int, C.POINTER(_Prm), C.c_double,
                                   C.c_double, dp, dp, dp, dp, dp, C.POINTER(C.c_int32)]
         L.oracle_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
         assert L.oracle_sizeof_fuel() == C.sizeof(_Fuel)
         assert L.oracle_sizeof_ign() == C.sizeof(_Ign)
         assert L.oracle_ncoef() == NCOEF
@@ -132,6 +134,11 @@ def _igns(igns):
 def threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Use ``n`` OpenMP threads in the oracle's loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- pieces

@@ -104,6 +104,16 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the oracle's parallel loops from now on (n >= 1). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 int oracle_sizeof_fuel(void) { return (int)sizeof(of_fuel); }
 int oracle_sizeof_ign(void) { return (int)sizeof(of_ign); }
 

@@ -83,3 +83,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_cpu_baseline_reports_one_thread_and_the_host():
+    """The oracle's host rate comes with its one-thread rate and the host's
+    processor, on a small patchy window (a few seconds of CPU)."""
+    import oracle
+    from paper_1102_1343_amd import synth
+
+    prob = synth.patchy_fire(256, steps=4)
+    before = oracle.threads()
+    r = bench.cpu_baseline(prob, "f64", 0.2)
+    assert oracle.threads() == before
+    assert r["kind"] == "oracle" and r["cores"] == before
+    st = r["single_thread"]
+    assert st["cores"] == 1 and st["value"] > 0 and st["threads_speedup_same_steps"] > 0
+    assert r["host"]["cpus_available"] >= 1 and isinstance(r["host"]["model"], str)

@@ -95,7 +95,7 @@ bool tile_ok(const fire_mesh *m, int tile_x, int tile_y) {
 namespace {
 
 struct Layout {
-    size_t coef, fuel, ign, status, psi0, psi1, tign, frac, total;
+    size_t coef, fuel, ign, geo, status, psi0, psi1, tign, frac, total;
 };
 
 Layout layout(const fire_mesh *m, int ncat) {
@@ -108,6 +108,8 @@ Layout layout(const fire_mesh *m, int ncat) {
     o = align_up(o + (size_t)ncat * sizeof(fire_fuel));
     L.ign = o;
     o = align_up(o + FIRE_MAX_IGNITIONS * sizeof(fire_ignition));
+    L.geo = o;
+    o = align_up(o + kIgnTableBytes);
     L.status = o;
     o = align_up(o + 64);
     L.psi0 = o;
@@ -165,6 +167,7 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     a.ros_cap = c->prm.ros_cap;
 
     StepBuffers b;
+    std::memset(&b, 0, sizeof(b));
     b.psi_in = psi_in;
     b.psi_out = psi_out;
     b.tign = tign;
@@ -179,6 +182,8 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     b.flat = flux_lat;
     b.status = status;
     b.ign = (const fire_ignition *)state_ptr(c, c->off_ign);
+    b.ign_tab = state_ptr(c, c->off_geo);
+    b.ndom = 1;
     b.ncells = (size_t)m.nx * m.ny;
     b.ens_doms = nullptr;
     b.ens_tile_dom = nullptr;
@@ -243,6 +248,7 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
     c->off_coef = L.coef;
     c->off_fuel = L.fuel;
     c->off_ign = L.ign;
+    c->off_geo = L.geo;
     c->off_status = L.status;
     c->off_psi[0] = L.psi0;
     c->off_psi[1] = L.psi1;

@@ -162,16 +162,13 @@ __device__ __forceinline__ T rhs5(T pc, T pw, T pe, T ps, T pn, T u, T v, T gzx,
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// One ignition's geometry at time t.  The segment start stays in double so
-// node offsets are formed exactly from global coordinates: psi_g at a node
-// is then the same in every tile that touches the node (owner or halo).
-template <typename T> struct IgnGeo {
-    double ax, ay;
-    T ex, ey, exL, eyL, rad, tg, lenv, invS, t, pad;
-};
-
+// One ignition's geometry at time t (IgnGeo): plain IEEE operations with no
+// contraction into fused multiply-adds, so every kernel that forms it (the
+// per-step table of the step kernels, the reverse kernels) gets the same
+// bits.
 template <typename T>
 __device__ __forceinline__ bool ign_setup(const fire_ignition &g, double t, IgnGeo<T> &o) {
+#pragma clang fp contract(off)
     const bool torch = (g.vx != 0.0 || g.vy != 0.0);
     const double tend = torch ? g.t_end : g.t_start;
     const bool inst = __builtin_isinf(g.ros);
@@ -248,32 +245,42 @@ template <> struct IgnMargin<double> {
     static __device__ __forceinline__ double v() { return 1.0 + 0x1p-40; }
 };
 
+// The same as ign_apply where psi_g > 0 is known for the node (a tile whose
+// lower bound of psi_g is positive): only p can change.
+template <typename T>
+__device__ __forceinline__ void ign_lower(const IgnGeo<T> &g, T px, T py, T by, T &p) {
+    const IgnNear<T> q = ign_near(g, px, py, by);
+    if (sizeof(T) == 8) {
+        const T pr = p + g.rad;
+        if (p > T(0) && q.d2 > pr * pr * IgnMargin<T>::v()) return;
+    }
+    const T pg = M<T>::sqrt(q.d2) - g.rad;
+    p = pg < p ? pg : p;   // a NaN p stays NaN
+}
+
 // Applies one ignition to node value p (Eq. 21): p := min(p, psi_g), with
 // psi_g = d - r_g of Eq. (20), and a node with psi_g <= 0 offers its arrival
-// time to tig (the minimum over ignitions).  Where p > 0 and d2 alone shows
-// psi_g >= p (so also psi_g > 0) neither can change and the square root is
-// skipped; the result is the same as without the test.  Returns bit 0 if p
+// time to tig (the minimum over ignitions).  FP32 evaluates every node
+// without branches (the square root costs less than the test that would
+// skip it); FP64, whose square root is a long sequence, skips it where p > 0
+// and d2 alone shows psi_g >= p (so also psi_g > 0): neither can change
+// there, so the result is the same as without the test.  Returns bit 0 if p
 // was lowered, bit 1 if tig was.
 template <typename T>
 __device__ __forceinline__ int ign_apply(const IgnGeo<T> &g, T px, T py, T by, T &p, T &tig) {
     const IgnNear<T> q = ign_near(g, px, py, by);
-    const T pr = p + g.rad;
-    if (p > T(0) && q.d2 > pr * pr * IgnMargin<T>::v()) return 0;
+    if (sizeof(T) == 8) {
+        const T pr = p + g.rad;
+        if (p > T(0) && q.d2 > pr * pr * IgnMargin<T>::v()) return 0;
+    }
     const T d = M<T>::sqrt(q.d2);
     const T pg = d - g.rad;
-    int changed = 0;
-    if (pg <= T(0)) {
-        const T a = ign_arrival(g, q, d);
-        if (a < tig) {
-            tig = a;
-            changed |= 2;
-        }
-    }
-    if (pg < p) {   // a NaN p stays NaN (reported by the status word)
-        p = pg;
-        changed |= 1;
-    }
-    return changed;
+    const T a = ign_arrival(g, q, d);
+    const bool lit = pg <= T(0) && a < tig;
+    const bool lower = pg < p;   // a NaN p stays NaN (reported by the status word)
+    tig = lit ? a : tig;
+    p = lower ? pg : p;
+    return (lit ? 2 : 0) | (lower ? 1 : 0);
 }
 
 }  // namespace dev

@@ -19,8 +19,8 @@ struct fire_ens {
     std::vector<int32_t> nign;
     std::vector<fire_ignition> ign_host;      // FIRE_MAX_IGNITIONS slots per member
     char *arena;
-    size_t off_coef, off_fuel, off_ign, off_dom, off_map, off_status, off_t, off_psi[2], off_tign,
-        off_frac, total;
+    size_t off_coef, off_fuel, off_ign, off_geo, off_dom, off_map, off_status, off_t, off_psi[2],
+        off_tign, off_frac, total;
     size_t map_cap;                            // capacity of the tile -> domain map
     const uint8_t *cat;
     const void *dzdx, *dzdy;
@@ -63,6 +63,8 @@ size_t layout(fire_ens *e) {
     o = align_up(o + (size_t)e->ncat * sizeof(fire_fuel));
     e->off_ign = o;
     o = align_up(o + (size_t)e->ndom * FIRE_MAX_IGNITIONS * sizeof(fire_ignition));
+    e->off_geo = o;
+    o = align_up(o + (size_t)e->ndom * kIgnTableBytes);
     e->off_dom = o;
     o = align_up(o + (size_t)e->ndom * sizeof(EnsDomain));
     // the work list is longest for the smallest tile (sr_x x sr_y): one entry
@@ -272,6 +274,8 @@ int fire_ens_step(fire_ens *e, const void *u, const void *v, double dt, void *fl
     b.status = (int *)ptr(e, e->off_status);
     b.ncells = (size_t)e->cell_off[e->ndom];
     b.ign = (const fire_ignition *)ptr(e, e->off_ign);
+    b.ign_tab = ptr(e, e->off_geo);
+    b.ndom = e->ndom;
     b.ens_doms = (const EnsDomain *)ptr(e, e->off_dom);
     b.ens_tile_dom = (const int32_t *)ptr(e, e->off_map);
     b.ens_clock = (const EnsClock *)ptr(e, e->off_t);

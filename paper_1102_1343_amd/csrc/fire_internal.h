@@ -45,6 +45,25 @@ struct StepArgs {
     double eps, ros_cap;
 };
 
+// One ignition's geometry at a time t (Sect. 4.4): the segment start in
+// double, so node offsets are formed exactly from global coordinates and
+// psi_g at a node is the same in every tile that touches the node; the
+// segment vector, its share of the projection (e / |e|^2), the current
+// radius, start time, drip-torch time per unit length, 1 / S_g and t.
+template <typename T> struct IgnGeo {
+    double ax, ay;
+    T ex, ey, exL, eyL, rad, tg, lenv, invS, t, pad;
+};
+
+// Geometry of a domain's ignitions for one step, formed once per step by a
+// small kernel ahead of the step kernel (on = active at that time).
+template <typename T> struct IgnTable {
+    IgnGeo<T> g[FIRE_MAX_IGNITIONS];
+    int32_t on[FIRE_MAX_IGNITIONS];
+};
+// bytes reserved per domain for its table (room for either precision)
+constexpr size_t kIgnTableBytes = (sizeof(IgnTable<double>) + 255) / 256 * 256;
+
 // One member of an ensemble (device table row).
 struct EnsDomain {
     int32_t nx, ny, tiles_x, tile0;     // tile0: first work-list tile of the domain
@@ -75,6 +94,9 @@ struct StepBuffers {
     int *status;
     const fire_ignition *ign;           // device ignition records: one domain's, or
                                         // FIRE_MAX_IGNITIONS per ensemble member
+    void *ign_tab;                      // kIgnTableBytes per domain: the step's
+                                        // ignition geometry (IgnTable)
+    int32_t ndom;                       // domains of an ensemble launch
     size_t ncells;                      // cells in the (concatenated) arrays
     const EnsDomain *ens_doms;          // non-null for an ensemble launch; then
     const int32_t *ens_tile_dom;        // psi_in / psi_out are the two buffers and
@@ -99,7 +121,7 @@ struct fire_ctx {
     const uint8_t *cat;
     const void *dzdx, *dzdy;
     char *arena;
-    size_t off_coef, off_fuel, off_ign, off_status, off_psi[2], off_tign, off_frac;
+    size_t off_coef, off_fuel, off_ign, off_geo, off_status, off_psi[2], off_tign, off_frac;
     int cur;               // index of the current psi buffer
     double t;              // model time of the current state
     hipStream_t stream;

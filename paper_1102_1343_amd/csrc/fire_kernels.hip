@@ -136,7 +136,7 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 template <typename T, int KR, bool SMALL, bool REC>
 __device__ __forceinline__ void
 step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double tnow,
-          const fire_ignition *ign, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
+          const IgnTable<T> *itab, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
           const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
           const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
           T *__restrict__ fsens, T *__restrict__ flat, int *status, T *rec_p0, T *rec_b,
@@ -216,19 +216,38 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
         tig[k] = INF;
     }
     if (a.nign > 0) {
-        // each ignition's geometry at t, once per work-group (lane g of the
-        // first wave takes ignition g), and its per-row offsets py, by for
-        // the frame rows, shared through LDS
+        // the step's geometry of each ignition (lane g of the first wave
+        // takes ignition g) and its per-row offsets py, by for the frame
+        // rows, shared through LDS
         __shared__ IgnGeo<T> geo_s[FIRE_MAX_IGNITIONS];
         __shared__ int geo_on[FIRE_MAX_IGNITIONS];
-        __shared__ int geo_use[FIRE_MAX_IGNITIONS];
+        __shared__ int geo_use[FIRE_MAX_IGNITIONS];   // 0 skip, 1 far, 2 near
+        __shared__ T geo_lb[FIRE_MAX_IGNITIONS], geo_ub[FIRE_MAX_IGNITIONS];
         __shared__ T wave_max[kBlock / 64];
         __shared__ T row_py[FIRE_MAX_IGNITIONS][FHM];
         __shared__ T row_by[FIRE_MAX_IGNITIONS][FHM];
         if (tid < a.nign) {
-            IgnGeo<T> gs;
-            geo_on[tid] = ign_setup<T>(ign[tid], tnow, gs) ? 1 : 0;
+            const IgnGeo<T> gs = itab->g[tid];
+            const bool on = itab->on[tid] != 0;
+            geo_on[tid] = on ? 1 : 0;
             geo_s[tid] = gs;
+            if (on) {
+                // bounds of psi_g over the frame nodes: distance from the
+                // frame's centre to the segment, -/+ its half diagonal, less
+                // the radius, widened by a margin (1 m + 1e-4 of the
+                // distances) far above the rounding of psi_g and of the
+                // bounds themselves
+                const T cx = T((x0 - kHalo + 0.5 * kFW - 0.5) * a.dx - gs.ax);
+                const T cy = T((y0 - kHalo + 0.5 * FHM - 0.5) * a.dy - gs.ay);
+                const T hx = T(0.5 * (kFW - 1)) * T(a.dx), hy = T(0.5 * (FHM - 1)) * T(a.dy);
+                const T hd = M<T>::sqrt(hx * hx + hy * hy);
+                const T sp = med3(cx * gs.exL + cy * gs.eyL, T(0), T(1));
+                const T qx = cx - sp * gs.ex, qy = cy - sp * gs.ey;
+                const T d = M<T>::sqrt(qx * qx + qy * qy);
+                const T mg = T(1) + T(1e-4) * (d + M<T>::sqrt(gs.ex * gs.ex + gs.ey * gs.ey));
+                geo_lb[tid] = d - hd - gs.rad - mg;
+                geo_ub[tid] = d + hd - gs.rad + mg;
+            }
         }
         // the frame's largest psi^n (NaN nodes, which no ignition changes,
         // are ignored): an ignition whose psi_g is provably positive and no
@@ -247,40 +266,44 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
                 row_by[g][j] = ign_by(geo_s[g], py);
             }
         }
-        if (tid < a.nign) geo_use[tid] = geo_on[tid];
-        if (tid < a.nign && geo_on[tid]) {
-            const IgnGeo<T> gs = geo_s[tid];
-            T M = wave_max[0];
-            for (int w = 1; w < kBlock / 64; w++) M = vmax(M, wave_max[w]);
-            // lower bound of psi_g over the frame nodes: distance from the
-            // frame's centre to the segment, less its half diagonal, the
-            // radius and a margin far above the rounding of psi_g
-            const double bx0 = (x0 - kHalo + 0.5) * a.dx;
-            const double bx1 = (x0 - kHalo + kFW - 0.5) * a.dx;
-            const double by0 = (y0 - kHalo + 0.5) * a.dy;
-            const double by1 = (y0 - kHalo + FHM - 0.5) * a.dy;
-            const double cx = 0.5 * (bx0 + bx1) - gs.ax, cy = 0.5 * (by0 + by1) - gs.ay;
-            const double ex = gs.ex, ey = gs.ey, L2 = ex * ex + ey * ey;
-            double sp = L2 > 0.0 ? (cx * ex + cy * ey) / L2 : 0.0;
-            sp = sp < 0.0 ? 0.0 : (sp > 1.0 ? 1.0 : sp);
-            const double qx = cx - sp * ex, qy = cy - sp * ey;
-            const double d = ::sqrt(qx * qx + qy * qy);
-            const double hd = 0.5 * ::sqrt((bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0));
-            const double lb = d - hd - (double)gs.rad - (1.0 + 1e-4 * (d + ::sqrt(L2)));
-            if (lb > 0.0 && lb >= (double)M) geo_use[tid] = 0;
+        if (tid < a.nign) {
+            int use = geo_on[tid] ? 2 : 0;
+            const T lb = geo_lb[tid];
+            if (use && lb > T(0)) {
+                // psi_g > 0 on every frame node: no node is lit by it.  It
+                // is never the minimum either when no smaller than the
+                // frame's largest psi^n, or above another active ignition's
+                // psi_g everywhere
+                use = 1;
+                T M = wave_max[0];
+                for (int w = 1; w < kBlock / 64; w++) M = vmax(M, wave_max[w]);
+                if (lb >= M) use = 0;
+                for (int h = 0; h < a.nign; h++)
+                    if (h != tid && geo_on[h] && geo_ub[h] < lb) use = 0;
+            }
+            geo_use[tid] = use;
         }
         __syncthreads();
         T pold[KR];
 #pragma unroll
         for (int k = 0; k < KR; k++) pold[k] = p0[k];
         for (int g = 0; g < a.nign; g++) {
-            if (!geo_use[g]) continue;
+            const int use = geo_use[g];
+            if (!use) continue;
             const IgnGeo<T> geo = geo_s[g];
             const T px = ign_px(geo, gx, a.dx);
+            if (use == 2) {
 #pragma unroll
-            for (int k = 0; k < KR; k++) {
-                const int fy = ty + kNR * k;
-                ign_apply(geo, px, row_py[g][fy], row_by[g][fy], p0[k], tig[k]);
+                for (int k = 0; k < KR; k++) {
+                    const int fy = ty + kNR * k;
+                    ign_apply(geo, px, row_py[g][fy], row_by[g][fy], p0[k], tig[k]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < KR; k++) {
+                    const int fy = ty + kNR * k;
+                    ign_lower(geo, px, row_py[g][fy], row_by[g][fy], p0[k]);
+                }
             }
         }
 #pragma unroll
@@ -510,7 +533,7 @@ template <typename T, int KR> constexpr int waves_per_simd() {
 // every node whose ignition time this step sets.
 template <typename T, int KR, bool SMALL, bool REC>
 __global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
-k_step(const StepArgs a, const fire_ignition *ign, const T *__restrict__ psi_in,
+k_step(const StepArgs a, const IgnTable<T> *itab, const T *__restrict__ psi_in,
        T *__restrict__ psi_out, T *tign, T *frac, const T *__restrict__ uw,
        const T *__restrict__ vw, const T *__restrict__ dzdx, const T *__restrict__ dzdy,
        const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
@@ -519,7 +542,7 @@ k_step(const StepArgs a, const fire_ignition *ign, const T *__restrict__ psi_in,
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
     if (tile >= a.ntiles) return;
-    step_tile<T, KR, SMALL, REC>(a, tile, 0u, a.t, ign, psi_in, psi_out, tign, frac, uw, vw,
+    step_tile<T, KR, SMALL, REC>(a, tile, 0u, a.t, itab, psi_in, psi_out, tign, frac, uw, vw,
                                  dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b,
                                  mark);
 }
@@ -533,7 +556,7 @@ template <typename T, int KR, bool SMALL>
 __global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
 k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
            const int32_t *__restrict__ tile_dom, const EnsClock *__restrict__ clock,
-           const fire_ignition *__restrict__ ign_all, T *psi_a,
+           const char *__restrict__ itabs, T *psi_a,
            T *psi_b, T *tign, T *frac, const T *__restrict__ uw, const T *__restrict__ vw,
            const T *__restrict__ dzdx, const T *__restrict__ dzdy,
            const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
@@ -558,9 +581,9 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
     a.dy = d.dy;
     a.rdx = d.rdx;
     a.rdy = d.rdy;
-    // a member's ignitions: FIRE_MAX_IGNITIONS records from ign_all + di * 8,
-    // indexed from the kernel argument so the loads stay global-memory loads
-    const fire_ignition *ign = ign_all + (size_t)di * FIRE_MAX_IGNITIONS;
+    // the member's ignition geometry for this step (kIgnTableBytes apart)
+    const IgnTable<T> *itab =
+        reinterpret_cast<const IgnTable<T> *>(itabs + (size_t)di * kIgnTableBytes);
     const double tnow = clock->t;
     const bool flip = clock->cur != 0;
     const T *pin = flip ? psi_b : psi_a;
@@ -569,17 +592,38 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
     if (SMALL) {
         // the member's first element goes into the 32-bit element index, so
         // the array bases stay the launch's (no per-member 64-bit pointers)
-        step_tile<T, KR, SMALL, false>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, ign, pin,
+        step_tile<T, KR, SMALL, false>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, itab, pin,
                                        pout, tign, frac, uw, vw, dzdx, dzdy, cat, coef,
                                        fsens + a0, flat + a0, status + di, nullptr, nullptr,
                                        nullptr);
     } else {
         const size_t c0 = (size_t)d.cell_off;
-        step_tile<T, KR, SMALL, false>(a, g - d.tile0, 0u, tnow, ign, pin + c0, pout + c0,
+        step_tile<T, KR, SMALL, false>(a, g - d.tile0, 0u, tnow, itab, pin + c0, pout + c0,
                                        tign + c0, frac + c0, uw + c0, vw + c0, dzdx + c0,
                                        dzdy + c0, cat + c0, coef, fsens + a0, flat + a0,
                                        status + di, nullptr, nullptr, nullptr);
     }
+}
+
+// The step's ignition geometry (IgnTable) of each domain, ahead of the step
+// kernel: one thread per (domain, ignition slot).  A single domain passes its
+// records and time; an ensemble its member table and device clock, each
+// member's records FIRE_MAX_IGNITIONS apart.
+template <typename T>
+__global__ void k_ign_geo(const fire_ignition *__restrict__ ign, int nign, double t,
+                          const EnsDomain *__restrict__ doms, const EnsClock *__restrict__ clock,
+                          int ndom, char *__restrict__ tabs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int di = i / FIRE_MAX_IGNITIONS, g = i - di * FIRE_MAX_IGNITIONS;
+    if (di >= ndom) return;
+    const int n = doms ? doms[di].nign : nign;
+    const double tt = doms ? clock->t : t;
+    IgnGeo<T> geo = {};
+    bool on = false;
+    if (g < n) on = ign_setup<T>(ign[(size_t)di * FIRE_MAX_IGNITIONS + g], tt, geo);
+    IgnTable<T> *tab = reinterpret_cast<IgnTable<T> *>(tabs + (size_t)di * kIgnTableBytes);
+    tab->g[g] = geo;
+    tab->on[g] = on ? 1 : 0;
 }
 
 // Advances an ensemble's device clock after its step kernel (stream order).
@@ -681,24 +725,35 @@ template <typename T, int KR, bool SMALL>
 hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     const size_t dyn = (size_t)a.ncat * kLRow * sizeof(T);
     const int grid = a.per_xcd * 8;
+    // the ignition geometry of the step: every step of an ensemble (its time
+    // is on the device), a single domain's only while an ignition is active
+    if (b.ens_doms || a.nign > 0) {
+        const int nth = (b.ens_doms ? b.ndom : 1) * FIRE_MAX_IGNITIONS;
+        hipLaunchKernelGGL((k_ign_geo<T>), dim3((nth + 63) / 64), dim3(64), 0, s, b.ign,
+                           a.nign, a.t, b.ens_doms, b.ens_clock, b.ens_doms ? b.ndom : 1,
+                           (char *)b.ign_tab);
+    }
     if (b.ens_doms) {
         hipLaunchKernelGGL((k_ens_step<T, KR, SMALL>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
-                           b.ens_doms, b.ens_tile_dom, b.ens_clock, b.ign, (T *)b.psi_in,
+                           b.ens_doms, b.ens_tile_dom, b.ens_clock, (const char *)b.ign_tab,
+                           (T *)b.psi_in,
                            (T *)b.psi_out, (T *)b.tign, (T *)b.frac, (const T *)b.u,
                            (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy, b.cat,
                            (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status);
     } else if (b.rec_p0) {
         hipLaunchKernelGGL((k_step<T, KR, SMALL, true>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
-                           b.ign, (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
-                           (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
-                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
-                           (T *)b.rec_p0, (T *)b.rec_b, (int32_t *)nullptr);
+                           (const IgnTable<T> *)b.ign_tab, (const T *)b.psi_in, (T *)b.psi_out,
+                           (T *)b.tign, (T *)b.frac, (const T *)b.u, (const T *)b.v,
+                           (const T *)b.dzdx, (const T *)b.dzdy, b.cat, (const T *)b.coef,
+                           (T *)b.fsens, (T *)b.flat, b.status, (T *)b.rec_p0, (T *)b.rec_b,
+                           (int32_t *)nullptr);
     } else {
         hipLaunchKernelGGL((k_step<T, KR, SMALL, false>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
-                           b.ign, (const T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
-                           (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
-                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
-                           (T *)nullptr, (T *)nullptr, b.mark);
+                           (const IgnTable<T> *)b.ign_tab, (const T *)b.psi_in, (T *)b.psi_out,
+                           (T *)b.tign, (T *)b.frac, (const T *)b.u, (const T *)b.v,
+                           (const T *)b.dzdx, (const T *)b.dzdy, b.cat, (const T *)b.coef,
+                           (T *)b.fsens, (T *)b.flat, b.status, (T *)nullptr, (T *)nullptr,
+                           b.mark);
     }
     return hipGetLastError();
 }

@@ -175,8 +175,9 @@ def main():
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
     ap.add_argument("--every", type=int, default=50,
                     help="adjoint workload: checkpoint interval (steps)")
-    ap.add_argument("--loop-steps", type=int, default=50,
-                    help="ensemble workload: steps of the loop of plain contexts to time")
+    ap.add_argument("--loop-steps", type=int, default=0,
+                    help="ensemble workload: steps of the loop of plain contexts to time "
+                         "(0: the same window as the ensemble)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -567,71 +568,87 @@ ENS_TILES = [(120, 20), (120, 10), (60, 20), (120, 30), (120, 40), (60, 10), (60
 
 def run_ensemble(args, probs, dtype):
     """All members in one launch per step (HIP graph replay of fire_ens_step),
-    against a loop of one plain fire_step per member and step."""
+    under both schedules of the step kernel (one work-group per tile; resident
+    work-groups), each from t = 0 over the same step window, against a loop of
+    one plain fire_step per member and step over that window too."""
     import numpy as np
     import torch
     from paper_1102_1343_amd import fire as F
 
     tdt = torch.float32 if dtype == "f32" else torch.float64
     stream = torch.cuda.current_stream()
-    ens = F.FireEnsemble.from_problems(probs, dtype=tdt)
-    u = ens.concat([p.wind[0][0] for p in probs])
-    v = ens.concat([p.wind[0][1] for p in probs])
-    fs, fl = ens.new_flux()
     dt = probs[0].dt
-    cells = ens.ncells
-    torch.cuda.synchronize()
-    if args.tile:
-        best = tuple(int(x) for x in args.tile.split(","))
-        ens.set_tile(*best)
-    else:
-        log(f"ensemble of {ens.ndom}, {cells} cells resident; autotuning tiles")
-        best = ens.autotune(u, v, dt, ENS_TILES, reps=3)
-    log(f"tile {best}; warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        ens.step(u, v, dt, fs, fl)
-    torch.cuda.synchronize()
+    K, W = args.steps, args.warmup
+    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
 
-    # capture one step; each replay is one step of every member
-    side = torch.cuda.Stream()
-    ens.set_stream(side)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(graph, stream=side):
+    def timed(resident):
+        ens = F.FireEnsemble.from_problems(probs, dtype=tdt)
+        u = ens.concat([p.wind[0][0] for p in probs])
+        v = ens.concat([p.wind[0][1] for p in probs])
+        fs, fl = ens.new_flux()
+        ens.set_schedule(resident)
+        torch.cuda.synchronize()
+        if tile is None:
+            log(f"ensemble of {ens.ndom}, {ens.ncells} cells resident; autotuning tiles "
+                f"({'resident' if resident else 'grid'} schedule)")
+            best = ens.autotune(u, v, dt, ENS_TILES, reps=3)
+        else:
+            best = tile
+            ens.set_tile(*best)
+        for _ in range(W):
             ens.step(u, v, dt, fs, fl)
-    ens.set_stream(stream)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        # capture one step; each replay is one step of every member
+        side = torch.cuda.Stream()
+        ens.set_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                ens.step(u, v, dt, fs, fl)
+        ens.set_stream(stream)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(K)]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for k in range(K):
+            ev[k][0].record(stream)
+            graph.replay()
+            ev[k][1].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        total_ms = t0.elapsed_time(t1)
+        step_us = [x.elapsed_time(y) * 1e3 for x, y in ev]
+        status = ens.status()
+        burning = float((ens.psi < 0).float().mean())
+        q = max(1, K // 10)
+        r = {"value": ens.ncells * K / (total_ms / 1e3), "ms_per_step": total_ms / K,
+             "avg_step_us": sum(step_us) / K, "first_tenth_us": sum(step_us[:q]) / q,
+             "last_tenth_us": sum(step_us[-q:]) / q, "flagged": int((status != 0).sum()),
+             "burning": burning, "cells": ens.ncells, "tile": list(best)}
+        log(f"resident {resident}, tile {best}: {K} graph steps in {total_ms:.2f} ms, avg "
+            f"{r['avg_step_us']:.1f} us/step (first tenth {r['first_tenth_us']:.1f}, last "
+            f"{r['last_tenth_us']:.1f}), {r['flagged']} members flagged, burning {burning:.4f}")
+        del graph
+        ens.close()
+        return r
 
-    K = args.steps
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(K)]
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    for k in range(K):
-        ev[k][0].record(stream)
-        graph.replay()
-        ev[k][1].record(stream)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    step_us = [a.elapsed_time(b) * 1e3 for a, b in ev]
-    avg_step_s = sum(step_us) / len(step_us) / 1e6
-    value = cells * K / (total_ms / 1e3)
-    status = ens.status()
-    burning = float((ens.psi < 0).float().mean())
-    q = max(1, K // 10)
-    log(f"{K} graph steps in {total_ms:.2f} ms, avg {avg_step_s * 1e6:.1f} us/step (first "
-        f"tenth {sum(step_us[:q]) / q:.1f}, last {sum(step_us[-q:]) / q:.1f}), "
-        f"{int((status != 0).sum())} members flagged, burning {burning:.4f}")
-    del graph
+    sched = {"grid": timed(False), "resident": timed(True)}
+    main_name = "grid"    # the library's default schedule
+    main = sched[main_name]
+    cells = main["cells"]
+    tile = tuple(main["tile"])
 
-    # the same members as plain contexts, one fire_step each per step
-    KL = max(1, min(args.loop_steps, K))
+    # the same members as plain contexts, one fire_step each per step, over
+    # the same window: W untimed steps, then K timed
     plain = [F.Fire.from_problem(p, dtype=tdt) for p in probs]
-    pw = [(ens.member(u, k), ens.member(v, k)) for k in range(len(probs))]
+    pw = [(torch.from_numpy(np.ascontiguousarray(p.wind[0][0])).to("cuda", tdt),
+           torch.from_numpy(np.ascontiguousarray(p.wind[0][1])).to("cuda", tdt)) for p in probs]
     pf = [g.new_flux() for g in plain]
-    for g, (uu, vv), (a, b) in zip(plain, pw, pf):
-        g.step(uu, vv, dt, a, b)
+    KL = K if args.loop_steps <= 0 else max(1, min(args.loop_steps, K))
+    for _ in range(W):
+        for g, (uu, vv), (a, b) in zip(plain, pw, pf):
+            g.step(uu, vv, dt, a, b)
     torch.cuda.synchronize()
     l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     l0.record(stream)
@@ -642,18 +659,20 @@ def run_ensemble(args, probs, dtype):
     torch.cuda.synchronize()
     loop_ms = l0.elapsed_time(l1)
     loop_value = cells * KL / (loop_ms / 1e3)
-    log(f"loop of {len(plain)} plain steps: {loop_ms / KL:.3f} ms/step")
+    log(f"loop of {len(plain)} plain steps over steps {W}..{W + KL - 1}: "
+        f"{loop_ms / KL:.3f} ms/step")
     for g in plain:
         g.close()
 
+    avg_step_s = main["avg_step_us"] / 1e6
     bytes_per_launch = B_ALG[dtype] * cells
     achieved = bytes_per_launch / avg_step_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": pmc_traffic(args.workload, dtype, best, kernel="k_ens_step"),
-            "kernel": "k_ens_step", "avg_kernel_us": round(avg_step_s * 1e6, 2),
+            "traffic": pmc_traffic(args.workload, dtype, tile, kernel="k_ens_step"),
+            "kernel": "k_ens_step", "avg_kernel_us": round(main["avg_step_us"], 2),
             "alg_bytes_per_cell_step": B_ALG[dtype],
-            "note": "duration per graph replay (step kernel + one-thread clock kernel)"}
+            "note": "duration per graph replay (geometry, step and one-thread clock kernels)"}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (cpu_baseline)")
@@ -662,12 +681,12 @@ def run_ensemble(args, probs, dtype):
     sides = [p.nx for p in probs]
     out = {
         "metric": "fire cell-steps/s",
-        "value": value,
+        "value": main["value"],
         "unit": "cell-steps/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": total_ms / K,
+        "warmup": W,
+        "ms_per_step": main["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -676,12 +695,15 @@ def run_ensemble(args, probs, dtype):
         "config": {"workload": f"ensemble256: {len(probs)} square fire domains, sides "
                                f"{min(sides)}-{max(sides)} (sum {cells} cells), dx=6 m, "
                                f"dt={dt} s, refinement 10, one HIP-graph replay per step",
-                   "members": len(probs), "cells": cells, "tile": list(best),
-                   "members_flagged": int((status != 0).sum()),
-                   "burning_frac_end": round(burning, 5)},
-        "ensemble": {"loop_value": loop_value, "loop_steps": KL,
+                   "members": len(probs), "cells": cells, "tile": list(tile),
+                   "schedule": main_name,
+                   "members_flagged": main["flagged"],
+                   "burning_frac_end": round(main["burning"], 5)},
+        "ensemble": {"schedules": sched, "loop_value": loop_value, "loop_steps": KL,
+                     "loop_window": [W, W + KL],
                      "loop_ms_per_step": loop_ms / KL,
-                     "speedup_vs_loop": value / loop_value},
+                     "speedup_vs_loop": main["value"] / loop_value,
+                     "resident_over_grid": sched["resident"]["value"] / sched["grid"]["value"]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -232,10 +232,21 @@ void fire_destroy(fire_ctx *ctx);
  * at element cell_off[k]; atmosphere arrays likewise at atm_off[k]
  * (fire_ens_layout()).  The model time and the index of the current psi
  * buffer live on the device (advanced by a one-thread kernel after each step),
- * so fire_ens_step() enqueues the same two kernels every call and may be
- * captured once in a HIP graph and replayed: each replay is one step.
+ * so fire_ens_step() enqueues the same three kernels every call (the step's
+ * ignition geometry, the step, the clock) and may be captured once in a HIP
+ * graph and replayed: each replay is one step.
+ *
+ * Two schedules of the step kernel, with the same results bit for bit:
+ *   FIRE_ENS_GRID     one work-group per tile of the members' work list
+ *                     (members in index order);
+ *   FIRE_ENS_RESIDENT as many work-groups as fit on the device at once, each
+ *                     taking tiles from a counter over its band of the work
+ *                     list, members ordered largest first.
  * ---------------------------------------------------------------------- */
 typedef struct fire_ens fire_ens;
+
+#define FIRE_ENS_GRID 0
+#define FIRE_ENS_RESIDENT 1
 
 /* Element offsets of the members' blocks: cell_off[ndom + 1] into per-cell
  * arrays and atm_off[ndom + 1] into atmosphere arrays (host arrays written by
@@ -264,7 +275,7 @@ int fire_ens_init(fire_ens **out, const fire_mesh *meshes, int32_t ndom, const f
 /* One step of length dt of every member, winds u, v as concatenated per-cell
  * arrays, fluxes into concatenated atmosphere arrays.  Never waits; the
  * boundary condition of a member only sets its status bits (boundary policy
- * 1 for all members).  Enqueues two kernels and nothing else. */
+ * 1 for all members).  Enqueues three kernels and nothing else. */
 int fire_ens_step(fire_ens *e, const void *u, const void *v, double dt, void *flux_sens,
                   void *flux_lat);
 
@@ -279,6 +290,13 @@ int fire_ens_status(fire_ens *e, int32_t *status);
  * (waits).  Not to be called during graph capture. */
 int fire_ens_set_tile(fire_ens *e, int32_t tile_x, int32_t tile_y);
 int fire_ens_get_tile(fire_ens *e, int32_t *tile_x, int32_t *tile_y);
+
+/* Schedule of the step kernel (FIRE_ENS_GRID, the default, or
+ * FIRE_ENS_RESIDENT); rebuilds the work list (waits).  FIRE_ERR_ARG for any
+ * other value; FIRE_ERR_HIP if the device's occupancy cannot be queried (the
+ * schedule is then unchanged).  Not to be called during graph capture. */
+int fire_ens_set_schedule(fire_ens *e, int32_t schedule);
+int fire_ens_get_schedule(fire_ens *e, int32_t *schedule);
 
 /* Device scratch bytes fire_ens_autotune() needs (a snapshot of the state). */
 size_t fire_ens_tune_bytes(fire_ens *e);

@@ -2,6 +2,7 @@
 // by one kernel launch per time step.  Arena layout, work-list construction,
 // device-side model time and the tile autotuner.  The method's arithmetic is
 // the same per-tile routine the single-domain kernel runs.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -19,13 +20,15 @@ struct fire_ens {
     std::vector<int32_t> nign;
     std::vector<fire_ignition> ign_host;      // FIRE_MAX_IGNITIONS slots per member
     char *arena;
-    size_t off_coef, off_fuel, off_ign, off_geo, off_dom, off_map, off_status, off_t, off_psi[2],
-        off_tign, off_frac, total;
+    size_t off_coef, off_fuel, off_ign, off_geo, off_cnt, off_dom, off_map, off_status, off_t,
+        off_psi[2], off_tign, off_frac, total;
     size_t map_cap;                            // capacity of the tile -> domain map
     const uint8_t *cat;
     const void *dzdx, *dzdy;
     hipStream_t stream;
     int tile_x, tile_y, ntiles;
+    int schedule;   // FIRE_ENS_GRID or FIRE_ENS_RESIDENT
+    int slots;      // resident work-groups of the current tile shape
 };
 
 namespace {
@@ -65,6 +68,8 @@ size_t layout(fire_ens *e) {
     o = align_up(o + (size_t)e->ndom * FIRE_MAX_IGNITIONS * sizeof(fire_ignition));
     e->off_geo = o;
     o = align_up(o + (size_t)e->ndom * kIgnTableBytes);
+    e->off_cnt = o;
+    o = align_up(o + 8 * sizeof(int32_t));
     e->off_dom = o;
     o = align_up(o + (size_t)e->ndom * sizeof(EnsDomain));
     // the work list is longest for the smallest tile (sr_x x sr_y): one entry
@@ -90,13 +95,22 @@ size_t layout(fire_ens *e) {
 
 char *ptr(fire_ens *e, size_t off) { return e->arena + off; }
 
-// Domain table and tile -> domain work list for the current tile shape.
+// Domain table and tile -> domain work list for the current tile shape and
+// schedule: members in index order on the grid schedule, largest first on
+// the resident one (so the bands end with small members' tiles).
 int build_worklist(fire_ens *e) {
     std::vector<EnsDomain> doms(e->ndom);
     std::vector<int32_t> map;
     map.reserve(e->map_cap);
+    std::vector<int> order(e->ndom);
+    for (int k = 0; k < e->ndom; k++) order[k] = k;
+    if (e->schedule == FIRE_ENS_RESIDENT)
+        std::stable_sort(order.begin(), order.end(), [e](int a, int b) {
+            return (int64_t)e->meshes[a].nx * e->meshes[a].ny >
+                   (int64_t)e->meshes[b].nx * e->meshes[b].ny;
+        });
     int tile0 = 0;
-    for (int k = 0; k < e->ndom; k++) {
+    for (int k : order) {
         const fire_mesh &m = e->meshes[k];
         EnsDomain &d = doms[k];
         std::memset(&d, 0, sizeof(d));
@@ -122,6 +136,11 @@ int build_worklist(fire_ens *e) {
     }
     if (map.size() > e->map_cap) return FIRE_ERR_ARG;
     e->ntiles = tile0;
+    e->slots = 0;
+    if (e->schedule == FIRE_ENS_RESIDENT) {
+        e->slots = persist_slots(e->dtype, e->tile_y, e->ncat, (size_t)e->cell_off[e->ndom]);
+        if (e->slots < 8) return FIRE_ERR_HIP;
+    }
     hipError_t h = hipMemcpyAsync(ptr(e, e->off_dom), doms.data(), doms.size() * sizeof(EnsDomain),
                                   hipMemcpyHostToDevice, e->stream);
     if (h == hipSuccess)
@@ -189,6 +208,7 @@ int fire_ens_init(fire_ens **out, const fire_mesh *meshes, int32_t ndom, const f
     e->dzdx = dzdx;
     e->dzdy = dzdy;
     e->stream = (hipStream_t)stream;
+    e->schedule = FIRE_ENS_GRID;
     default_tile(&meshes[0], &e->tile_x, &e->tile_y);
     if (!tile_ok(&meshes[0], e->tile_x, e->tile_y)) {
         delete e;
@@ -276,6 +296,8 @@ int fire_ens_step(fire_ens *e, const void *u, const void *v, double dt, void *fl
     b.ign = (const fire_ignition *)ptr(e, e->off_ign);
     b.ign_tab = ptr(e, e->off_geo);
     b.ndom = e->ndom;
+    b.ens_counters = (int32_t *)ptr(e, e->off_cnt);
+    b.ens_slots = e->schedule == FIRE_ENS_RESIDENT ? e->slots : 0;
     b.ens_doms = (const EnsDomain *)ptr(e, e->off_dom);
     b.ens_tile_dom = (const int32_t *)ptr(e, e->off_map);
     b.ens_clock = (const EnsClock *)ptr(e, e->off_t);
@@ -318,6 +340,24 @@ int fire_ens_set_tile(fire_ens *e, int32_t tile_x, int32_t tile_y) {
     e->tile_x = tile_x;
     e->tile_y = tile_y;
     return build_worklist(e);
+}
+
+int fire_ens_set_schedule(fire_ens *e, int32_t schedule) {
+    if (!e || (schedule != FIRE_ENS_GRID && schedule != FIRE_ENS_RESIDENT)) return FIRE_ERR_ARG;
+    const int old = e->schedule;
+    e->schedule = schedule;
+    const int rc = build_worklist(e);
+    if (rc != FIRE_OK) {
+        e->schedule = old;
+        (void)build_worklist(e);
+    }
+    return rc;
+}
+
+int fire_ens_get_schedule(fire_ens *e, int32_t *schedule) {
+    if (!e || !schedule) return FIRE_ERR_ARG;
+    *schedule = e->schedule;
+    return FIRE_OK;
 }
 
 int fire_ens_get_tile(fire_ens *e, int32_t *tile_x, int32_t *tile_y) {

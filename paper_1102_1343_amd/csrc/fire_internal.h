@@ -101,6 +101,8 @@ struct StepBuffers {
     const EnsDomain *ens_doms;          // non-null for an ensemble launch; then
     const int32_t *ens_tile_dom;        // psi_in / psi_out are the two buffers and
     const EnsClock *ens_clock;          // the clock says which is current
+    int32_t *ens_counters;              // 8 work counters (resident work-groups)
+    int32_t ens_slots;                  // > 0: resident work-groups (k_ens_persist)
     void *rec_p0, *rec_b;               // non-null: a replay that writes psi^{n+1}, psi'
                                         // and psi* only (one domain)
     int32_t *mark;                      // non-null (plain step): mark[i] = mark_step at
@@ -154,6 +156,8 @@ hipError_t launch_ros_eval(int dtype, const void *coef, int ncat, double ros_cap
                            int64_t n, hipStream_t s);
 hipError_t launch_coef_to_f64(int dtype, const void *coef, double *out, int n, hipStream_t s);
 hipError_t launch_advance_clock(EnsClock *c, double dt, hipStream_t s);
+// resident work-groups of the ensemble step for this tile height (0: query failed)
+int persist_slots(int dtype, int tile_y, int ncat, size_t ncells);
 
 // ---- host helpers shared by the single-domain and ensemble ABI layers
 constexpr size_t kAlign = 256;

@@ -135,7 +135,8 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 // psi*, then the sensible flux; C holds the node ignition times t^.
 template <typename T, int KR, bool SMALL, bool REC>
 __device__ __forceinline__ void
-step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double tnow,
+step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const uint32_t cbase,
+          const double tnow,
           const IgnTable<T> *itab, const T *__restrict__ psi_in, T *__restrict__ psi_out, T *tign, T *frac,
           const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
           const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
@@ -153,7 +154,6 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     const int tyi = tile / a.tiles_x;
     const int txi = tile - tyi * a.tiles_x;
     const int x0 = txi * a.tile_x, y0 = tyi * a.tile_y;
-    const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * kFW + tx;
     const int nx = a.nx, ny = a.ny;
     const int FH = a.tile_y + 2 * kHalo;
@@ -176,7 +176,7 @@ step_tile(const StepArgs &a, const int tile, const uint32_t cbase, const double 
     // its rows (row k of the thread is fy = ty + kNR k): idx0 + k rstep, so
     // the per-row multiply is uniform (scalar) work
     const uint32_t idx0 = off0 + (uint32_t)ty * unx;
-    const uint32_t rstep = (uint32_t)kNR * unx;
+    const uint32_t rstep = __builtin_amdgcn_readfirstlane((uint32_t)kNR * unx);
     // k rstep held in a scalar register the compiler cannot see into (an
     // empty asm): a full-rate vector add per row rather than a 64-bit
     // multiply-add rebuilt from nx
@@ -542,7 +542,8 @@ k_step(const StepArgs a, const IgnTable<T> *itab, const T *__restrict__ psi_in,
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
     if (tile >= a.ntiles) return;
-    step_tile<T, KR, SMALL, REC>(a, tile, 0u, a.t, itab, psi_in, psi_out, tign, frac, uw, vw,
+    step_tile<T, KR, SMALL, REC>(a, tile, threadIdx.x, threadIdx.y, 0u, a.t, itab, psi_in,
+                                 psi_out, tign, frac, uw, vw,
                                  dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b,
                                  mark);
 }
@@ -552,18 +553,19 @@ k_step(const StepArgs a, const IgnTable<T> *itab, const T *__restrict__ psi_in,
 // work-group finds its domain, whose arrays sit at that domain's offsets in
 // the concatenated buffers.  The model time is read from device memory so a
 // step can be captured once and replayed.
+// Work-list tile g of an ensemble launch: finds its member, whose arrays sit
+// at that member's offsets in the concatenated buffers, and steps the tile.
+// The model time is read from device memory so a step can be captured once
+// and replayed.
 template <typename T, int KR, bool SMALL>
-__global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
-k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
-           const int32_t *__restrict__ tile_dom, const EnsClock *__restrict__ clock,
-           const char *__restrict__ itabs, T *psi_a,
-           T *psi_b, T *tign, T *frac, const T *__restrict__ uw, const T *__restrict__ vw,
-           const T *__restrict__ dzdx, const T *__restrict__ dzdy,
-           const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
-           T *__restrict__ flat, int *status) {
-    const int bid = blockIdx.x;
-    const int g = (bid & 7) * common.per_xcd + (bid >> 3);
-    if (g >= common.ntiles) return;
+__device__ __forceinline__ void
+ens_tile(const StepArgs &common, const int g, const int tx, const int ty,
+         const EnsDomain *__restrict__ doms,
+         const int32_t *__restrict__ tile_dom, const EnsClock *__restrict__ clock,
+         const char *__restrict__ itabs, T *psi_a, T *psi_b, T *tign, T *frac,
+         const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
+         const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
+         T *__restrict__ fsens, T *__restrict__ flat, int *status) {
     // one member per work-group: keep its index (and so every field of its
     // table row) in scalar registers
     const int di = __builtin_amdgcn_readfirstlane(tile_dom[g]);
@@ -592,16 +594,86 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
     if (SMALL) {
         // the member's first element goes into the 32-bit element index, so
         // the array bases stay the launch's (no per-member 64-bit pointers)
-        step_tile<T, KR, SMALL, false>(a, g - d.tile0, (uint32_t)d.cell_off, tnow, itab, pin,
+        step_tile<T, KR, SMALL, false>(a, g - d.tile0, tx, ty, (uint32_t)d.cell_off, tnow, itab,
+                                       pin,
                                        pout, tign, frac, uw, vw, dzdx, dzdy, cat, coef,
                                        fsens + a0, flat + a0, status + di, nullptr, nullptr,
                                        nullptr);
     } else {
         const size_t c0 = (size_t)d.cell_off;
-        step_tile<T, KR, SMALL, false>(a, g - d.tile0, 0u, tnow, itab, pin + c0, pout + c0,
+        step_tile<T, KR, SMALL, false>(a, g - d.tile0, tx, ty, 0u, tnow, itab, pin + c0,
+                                       pout + c0,
                                        tign + c0, frac + c0, uw + c0, vw + c0, dzdx + c0,
                                        dzdy + c0, cat + c0, coef, fsens + a0, flat + a0,
                                        status + di, nullptr, nullptr, nullptr);
+    }
+}
+
+// An ensemble of domains in one launch, one work-group per tile: the tiles of
+// all members form one work list (member-major), mapped onto the XCDs like a
+// single domain.
+template <typename T, int KR, bool SMALL>
+__global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
+k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
+           const int32_t *__restrict__ tile_dom, const EnsClock *__restrict__ clock,
+           const char *__restrict__ itabs, T *psi_a, T *psi_b, T *tign, T *frac,
+           const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
+           const T *__restrict__ dzdy, const uint8_t *__restrict__ cat,
+           const T *__restrict__ coef, T *__restrict__ fsens, T *__restrict__ flat,
+           int *status) {
+    const int bid = blockIdx.x;
+    const int g = (bid & 7) * common.per_xcd + (bid >> 3);
+    if (g >= common.ntiles) return;
+    ens_tile<T, KR, SMALL>(common, g, threadIdx.x, threadIdx.y, doms, tile_dom, clock, itabs,
+                           psi_a, psi_b, tign, frac, uw, vw, dzdx, dzdy, cat, coef, fsens, flat,
+                           status);
+}
+
+// The same step with resident work-groups: the grid is as many work-groups
+// as fit on the device at once, and each takes tiles of its XCD's band of the
+// work list (band = blockIdx % 8, as in k_ens_step) from a per-band counter
+// until the band is done.  The counters are cleared by k_ign_geo, which runs
+// before this kernel in stream order.  The next tile index is fetched while
+// the current tile computes; every work-group leaves once its band's counter
+// has passed the band's end, so the grid drains whatever its size.
+// Waves per SIMD asked of the resident kernel: as for the one-shot kernels,
+// and for the taller FP32 frames (KR >= 9, two work-groups per CU by LDS) the
+// four waves that two work-groups need.
+template <typename T, int KR> constexpr int persist_waves() {
+    return (sizeof(T) == 4 && KR >= 9) ? 4 : waves_per_simd<T, KR>();
+}
+
+template <typename T, int KR, bool SMALL>
+__global__ void __launch_bounds__(kBlock, (persist_waves<T, KR>()))
+k_ens_persist(const StepArgs common, const EnsDomain *__restrict__ doms,
+              const int32_t *__restrict__ tile_dom, const EnsClock *__restrict__ clock,
+              const char *__restrict__ itabs, T *psi_a, T *psi_b, T *tign, T *frac,
+              const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
+              const T *__restrict__ dzdy, const uint8_t *__restrict__ cat,
+              const T *__restrict__ coef, T *__restrict__ fsens, T *__restrict__ flat,
+              int *status, int32_t *counters) {
+    __shared__ int next_tile;
+    const int band = blockIdx.x & 7;
+    const int lo = band * common.per_xcd;
+    const int hi = min(lo + common.per_xcd, common.ntiles);
+    const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+    int mine = 0;
+    if (lead) mine = lo + atomicAdd(&counters[band], 1);
+    for (;;) {
+        // the previous tile's last reads of next_tile came before its first
+        // barrier, so the leader may overwrite it here
+        if (lead) next_tile = mine;
+        __syncthreads();
+        const int g = next_tile;
+        if (g >= hi) break;
+        if (lead) mine = lo + atomicAdd(&counters[band], 1);
+        // the thread's frame coordinates pass through an opaque copy each
+        // tile, so values derived from them are formed inside the loop rather
+        // than held in registers across it
+        int tx = threadIdx.x, ty = threadIdx.y;
+        asm volatile("" : "+v"(tx), "+v"(ty));
+        ens_tile<T, KR, SMALL>(common, g, tx, ty, doms, tile_dom, clock, itabs, psi_a, psi_b,
+                               tign, frac, uw, vw, dzdx, dzdy, cat, coef, fsens, flat, status);
     }
 }
 
@@ -612,8 +684,10 @@ k_ens_step(const StepArgs common, const EnsDomain *__restrict__ doms,
 template <typename T>
 __global__ void k_ign_geo(const fire_ignition *__restrict__ ign, int nign, double t,
                           const EnsDomain *__restrict__ doms, const EnsClock *__restrict__ clock,
-                          int ndom, char *__restrict__ tabs) {
+                          int ndom, char *__restrict__ tabs, int32_t *counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // work counters of a resident-work-group ensemble step start at zero
+    if (counters && i < 8) counters[i] = 0;
     const int di = i / FIRE_MAX_IGNITIONS, g = i - di * FIRE_MAX_IGNITIONS;
     if (di >= ndom) return;
     const int n = doms ? doms[di].nign : nign;
@@ -731,9 +805,16 @@ hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
         const int nth = (b.ens_doms ? b.ndom : 1) * FIRE_MAX_IGNITIONS;
         hipLaunchKernelGGL((k_ign_geo<T>), dim3((nth + 63) / 64), dim3(64), 0, s, b.ign,
                            a.nign, a.t, b.ens_doms, b.ens_clock, b.ens_doms ? b.ndom : 1,
-                           (char *)b.ign_tab);
+                           (char *)b.ign_tab, b.ens_slots > 0 ? b.ens_counters : nullptr);
     }
-    if (b.ens_doms) {
+    if (b.ens_doms && b.ens_slots > 0) {
+        hipLaunchKernelGGL((k_ens_persist<T, KR, SMALL>), dim3(b.ens_slots), dim3(kFW, kNR), dyn,
+                           s, a, b.ens_doms, b.ens_tile_dom, b.ens_clock, (const char *)b.ign_tab,
+                           (T *)b.psi_in, (T *)b.psi_out, (T *)b.tign, (T *)b.frac,
+                           (const T *)b.u, (const T *)b.v, (const T *)b.dzdx, (const T *)b.dzdy,
+                           b.cat, (const T *)b.coef, (T *)b.fsens, (T *)b.flat, b.status,
+                           b.ens_counters);
+    } else if (b.ens_doms) {
         hipLaunchKernelGGL((k_ens_step<T, KR, SMALL>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
                            b.ens_doms, b.ens_tile_dom, b.ens_clock, (const char *)b.ign_tab,
                            (T *)b.psi_in,
@@ -783,7 +864,45 @@ hipError_t step_t(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// Work-groups of k_ens_persist resident on the current device at once
+// (occupancy times compute units, rounded down to a multiple of the eight
+// XCD bands; 0 if the query fails).
+template <typename T, int KR>
+int persist_slots_k(int ncat, size_t ncells) {
+    const size_t dyn = (size_t)ncat * kLRow * sizeof(T);
+    const bool small = (uint64_t)ncells * sizeof(T) < ((uint64_t)1 << 32);
+    int nb = 0, dev = 0, ncu = 0;
+    const void *fn = small ? (const void *)k_ens_persist<T, KR, true>
+                           : (const void *)k_ens_persist<T, KR, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, dyn) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return nb * ncu / 8 * 8;
+}
+
+template <typename T> int persist_slots_t(int tile_y, int ncat, size_t ncells) {
+    const int fh = tile_y + 2 * kHalo;
+    if (fh <= 16) return persist_slots_k<T, 4>(ncat, ncells);
+    if (fh <= 20) return persist_slots_k<T, 5>(ncat, ncells);
+    if (fh <= 24) return persist_slots_k<T, 6>(ncat, ncells);
+    if (fh <= 28) return persist_slots_k<T, 7>(ncat, ncells);
+    if (fh <= 32) return persist_slots_k<T, 8>(ncat, ncells);
+    if constexpr (sizeof(T) == 4) {
+        if (fh <= 36) return persist_slots_k<T, 9>(ncat, ncells);
+        if (fh <= 40) return persist_slots_k<T, 10>(ncat, ncells);
+        if (fh <= 44) return persist_slots_k<T, 11>(ncat, ncells);
+        return persist_slots_k<T, 12>(ncat, ncells);
+    }
+    return 0;
+}
+
 }  // namespace
+
+int persist_slots(int dtype, int tile_y, int ncat, size_t ncells) {
+    return dtype == FIRE_F64 ? persist_slots_t<double>(tile_y, ncat, ncells)
+                             : persist_slots_t<float>(tile_y, ncat, ncells);
+}
 
 hipError_t launch_step(int dtype, const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     return dtype == FIRE_F64 ? step_t<double>(a, b, s) : step_t<float>(a, b, s);

@@ -22,6 +22,8 @@ ERR_BOUNDARY = -4
 ERR_NONFINITE = -5
 ERR_TOO_LARGE = -7
 WIND_STATIC_BYTES = 16 << 20
+ENS_GRID = 0          # fire_ens_set_schedule: one work-group per tile
+ENS_RESIDENT = 1      # resident work-groups over per-band tile counters
 MAX_IGNITIONS = 8
 NCOEF = 10
 COEF_NAMES = ("S0", "R0", "b", "c", "d", "e", "m", "Tf", "Ch", "Cq")
@@ -111,6 +113,8 @@ def lib():
         L.fire_ens_status.argtypes = [vp, i32p]
         L.fire_ens_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
         L.fire_ens_get_tile.argtypes = [vp, i32p, i32p]
+        L.fire_ens_set_schedule.argtypes = [vp, C.c_int32]
+        L.fire_ens_get_schedule.argtypes = [vp, i32p]
         L.fire_ens_tune_bytes.argtypes = [vp]
         L.fire_ens_tune_bytes.restype = C.c_size_t
         L.fire_ens_autotune.argtypes = [vp, vp, vp, C.c_double, vp, vp, i32p, C.c_int32,
@@ -541,6 +545,17 @@ class FireEnsemble:
         a, b = C.c_int32(), C.c_int32()
         _check(lib().fire_ens_get_tile(self._h, C.byref(a), C.byref(b)), "fire_ens_get_tile")
         return a.value, b.value
+
+    def set_schedule(self, resident: bool):
+        """One work-group per tile (False, the default) or resident
+        work-groups taking tiles from per-band counters (True)."""
+        _check(lib().fire_ens_set_schedule(self._h, ENS_RESIDENT if resident else ENS_GRID),
+               "fire_ens_set_schedule")
+
+    def get_schedule(self) -> bool:
+        a = C.c_int32()
+        _check(lib().fire_ens_get_schedule(self._h, C.byref(a)), "fire_ens_get_schedule")
+        return a.value == ENS_RESIDENT
 
     def autotune(self, u, v, dt, candidates, reps=5):
         """Time each (tile_x, tile_y) candidate, keep the fastest; the state is

@@ -2,8 +2,9 @@
 
 Each member of an ensemble must compute exactly what a single-domain context
 computes on its inputs: psi, t_i, F and both fluxes are compared bit for bit
-against one plain context per member, for several tile shapes, after
-autotuning, and under HIP-graph replay.  Members are also checked against
+against one plain context per member, for several tile shapes and both
+schedules of the step kernel (one work-group per tile; resident work-groups
+over per-band tile counters), after autotuning, and under HIP-graph replay.  Members are also checked against
 the FP64 oracle to the FP64 bar.
 """
 from __future__ import annotations
@@ -81,16 +82,20 @@ def test_ensemble_members_bitwise_equal_plain(dtype):
     ref = _plain_run(probs, dtype, steps)
     tiles = [None, (60, 10), (120, 30) if dtype == torch.float32 else (120, 20), (10, 10)]
     for tile in tiles:
-        ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
-        if tile:
-            ens.set_tile(*tile)
-        u, v = _ens_wind(ens, probs)
-        fs, fl = ens.new_flux()
-        for _ in range(steps):
-            ens.step(u, v, probs[0].dt, fs, fl)
-        torch.cuda.synchronize()
-        _assert_members_equal(ens, ref, fs, fl, f"tile {ens.get_tile()}")
-        ens.close()
+        for resident in (False, True):
+            ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
+            if tile:
+                ens.set_tile(*tile)
+            ens.set_schedule(resident)
+            assert ens.get_schedule() == resident
+            u, v = _ens_wind(ens, probs)
+            fs, fl = ens.new_flux()
+            for _ in range(steps):
+                ens.step(u, v, probs[0].dt, fs, fl)
+            torch.cuda.synchronize()
+            _assert_members_equal(ens, ref, fs, fl,
+                                  f"tile {ens.get_tile()}, resident {resident}")
+            ens.close()
     assert sum(np.isfinite(host(r[1])).sum() for r in ref) > 100
 
 
@@ -136,12 +141,14 @@ def test_ensemble_autotune_restores_state():
     _assert_members_equal(ens, ref, fs, fl, "after autotune")
 
 
-def test_ensemble_graph_replay():
+@pytest.mark.parametrize("resident", [False, True], ids=["grid", "resident"])
+def test_ensemble_graph_replay(resident):
     dtype = torch.float32
     probs = _members(7, 30, 200, 404, dtype)
     steps = 10
     ref = _plain_run(probs, dtype, steps)
     ens = F.FireEnsemble.from_problems(probs, dtype=dtype)
+    ens.set_schedule(resident)
     u, v = _ens_wind(ens, probs)
     fs, fl = ens.new_flux()
     ens.step(u, v, probs[0].dt, fs, fl)    # one eager step, then graph replays
@@ -187,44 +194,52 @@ def test_ensemble256_members_bitwise_after_500_steps():
     """The benchmark's ensemble (256 members of side 256-1024, 500 steps, FP32)
     in the benchmark's launch configuration -- autotuned tile, one HIP-graph
     replay per step -- against plain contexts on the same inputs, bit for bit,
-    for the smallest and largest members and two more."""
+    for the smallest and largest members and two more; under both schedules
+    (the resident one on the tile the autotuner picked for the grid one)."""
     probs = synth.ensemble(ndom=256, side_min=256, side_max=1024, steps=500,
                            field_dtype=np.float32)
     steps = probs[0].steps
     sides = np.array([p.nx * p.ny for p in probs])
     pick = sorted({int(np.argmin(sides)), int(np.argmax(sides)), 97, 200})
     _log(f"ensemble256: members {pick} (sides {[probs[k].nx for k in pick]})")
-    ens = F.FireEnsemble.from_problems(probs, dtype=torch.float32)
-    u, v = _ens_wind(ens, probs)
-    fs, fl = ens.new_flux()
-    tile = ens.autotune(u, v, probs[0].dt, [(120, 20), (120, 40), (60, 20)], reps=2)
-    stream = torch.cuda.current_stream()
-    side = torch.cuda.Stream()
-    ens.set_stream(side)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(graph, stream=side):
-            ens.step(u, v, probs[0].dt, fs, fl)
-    ens.set_stream(stream)
-    torch.cuda.synchronize()
-    for _ in range(steps):
-        graph.replay()
-    torch.cuda.synchronize()
-    _log(f"tile {tile}, {steps} graph replays done")
     ref = _plain_run([probs[k] for k in pick], torch.float32, steps)
-    st = ens.status()
-    for j, k in enumerate(pick):
-        psi, tig, frac, rfs, rfl, rst, rt = ref[j]
-        for name, a, b in (("psi", ens.member(ens.psi, k), psi),
-                           ("tign", ens.member(ens.tign, k), tig),
-                           ("frac", ens.member(ens.frac, k), frac),
-                           ("flux_sens", ens.member(fs, k, atm=True), rfs),
-                           ("flux_lat", ens.member(fl, k, atm=True), rfl)):
-            ia = a.contiguous().view(torch.int32)
-            ib = b.contiguous().view(torch.int32)
-            nbad = int((ia != ib).sum())
-            assert nbad == 0, f"member {k} {name}: {nbad} elements differ"
-        assert st[k] == rst
-        assert int((ref[j][2] < 1).sum()) > 100, f"member {k} has no burnt cells"
-    assert abs(ens.t - ref[0][6]) == 0.0
-    del graph
+    tile = None
+    for resident in (False, True):
+        ens = F.FireEnsemble.from_problems(probs, dtype=torch.float32)
+        u, v = _ens_wind(ens, probs)
+        fs, fl = ens.new_flux()
+        if tile is None:
+            tile = ens.autotune(u, v, probs[0].dt, [(120, 20), (120, 40), (60, 20)], reps=2)
+        else:
+            ens.set_tile(*tile)
+        ens.set_schedule(resident)
+        stream = torch.cuda.current_stream()
+        side = torch.cuda.Stream()
+        ens.set_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                ens.step(u, v, probs[0].dt, fs, fl)
+        ens.set_stream(stream)
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        _log(f"tile {tile}, resident {resident}: {steps} graph replays done")
+        st = ens.status()
+        for j, k in enumerate(pick):
+            psi, tig, frac, rfs, rfl, rst, rt = ref[j]
+            for name, a, b in (("psi", ens.member(ens.psi, k), psi),
+                               ("tign", ens.member(ens.tign, k), tig),
+                               ("frac", ens.member(ens.frac, k), frac),
+                               ("flux_sens", ens.member(fs, k, atm=True), rfs),
+                               ("flux_lat", ens.member(fl, k, atm=True), rfl)):
+                ia = a.contiguous().view(torch.int32)
+                ib = b.contiguous().view(torch.int32)
+                nbad = int((ia != ib).sum())
+                assert nbad == 0, f"resident {resident}: member {k} {name}: {nbad} differ"
+            assert st[k] == rst
+            assert int((ref[j][2] < 1).sum()) > 100, f"member {k} has no burnt cells"
+        assert abs(ens.t - ref[0][6]) == 0.0
+        del graph
+        ens.close()

@@ -640,13 +640,14 @@ def run_ensemble(args, probs, dtype):
     tile = tuple(main["tile"])
 
     # the same members as plain contexts, one fire_step each per step, over
-    # the same window: W untimed steps, then K timed
+    # the same window (W untimed steps, then K timed); --loop-steps L > 0
+    # times L steps after one untimed step instead (a short check)
     plain = [F.Fire.from_problem(p, dtype=tdt) for p in probs]
     pw = [(torch.from_numpy(np.ascontiguousarray(p.wind[0][0])).to("cuda", tdt),
            torch.from_numpy(np.ascontiguousarray(p.wind[0][1])).to("cuda", tdt)) for p in probs]
     pf = [g.new_flux() for g in plain]
-    KL = K if args.loop_steps <= 0 else max(1, min(args.loop_steps, K))
-    for _ in range(W):
+    KL, WL = (K, W) if args.loop_steps <= 0 else (max(1, min(args.loop_steps, K)), 1)
+    for _ in range(WL):
         for g, (uu, vv), (a, b) in zip(plain, pw, pf):
             g.step(uu, vv, dt, a, b)
     torch.cuda.synchronize()
@@ -659,7 +660,7 @@ def run_ensemble(args, probs, dtype):
     torch.cuda.synchronize()
     loop_ms = l0.elapsed_time(l1)
     loop_value = cells * KL / (loop_ms / 1e3)
-    log(f"loop of {len(plain)} plain steps over steps {W}..{W + KL - 1}: "
+    log(f"loop of {len(plain)} plain steps over steps {WL}..{WL + KL - 1}: "
         f"{loop_ms / KL:.3f} ms/step")
     for g in plain:
         g.close()
@@ -700,7 +701,7 @@ def run_ensemble(args, probs, dtype):
                    "members_flagged": main["flagged"],
                    "burning_frac_end": round(main["burning"], 5)},
         "ensemble": {"schedules": sched, "loop_value": loop_value, "loop_steps": KL,
-                     "loop_window": [W, W + KL],
+                     "loop_window": [WL, WL + KL],
                      "loop_ms_per_step": loop_ms / KL,
                      "speedup_vs_loop": main["value"] / loop_value,
                      "resident_over_grid": sched["resident"]["value"] / sched["grid"]["value"]},

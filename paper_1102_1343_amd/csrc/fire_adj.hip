@@ -55,6 +55,32 @@ __device__ __forceinline__ int ext_idx(const AdjArgs &a, int x, int y) {
     return (y + 1) * (a.nx + 2) + (x + 1);
 }
 
+// Per-block flags of the reverse pass (block b = nodes b kAB .. b kAB + kAB - 1):
+// nonzero where the block's values of dL/dpsi^{n+1} (L1), dL/dpsi* (LB),
+// the crossing part of dL/dpsi' (LP0) or dL/dt_i (LT) may be nonzero.  The
+// adjoint of a run is nonzero only where the final fuel fraction depends on
+// the state, a region that shrinks towards the ignitions as the steps are
+// reversed; a block whose inputs are all zero has all-zero outputs, so it
+// skips its work and writes only the zeros that stale values need.
+struct AdjFlags {
+    int32_t *l1, *lb, *lp0, *lt;
+};
+
+// Whether any block holding a node within one row or column of block b's
+// nodes (the reach of the stencil gathers, the ghost transposes included)
+// has its flag set.
+__device__ __forceinline__ bool nbhd_flag(const int32_t *f, const AdjArgs &a, int b) {
+    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
+    const int lo = b * kAB, hi = min(lo + kAB, nn) - 1;
+    auto blk = [&](int i) { return (i < 0 || i >= nn) ? -1 : i / kAB; };
+    const int c[7] = {b - 1, b, b + 1, blk(lo - a.nx), blk(hi - a.nx), blk(lo + a.nx),
+                      blk(hi + a.nx)};
+    bool any = false;
+    for (int k = 0; k < 7; k++)
+        if (c[k] >= 0 && c[k] < nb && f[c[k]]) any = true;
+    return any;
+}
+
 // d ghost(p, q) / d(p, q): ghost = 2p - q when p >= q, else q.
 template <typename T> __device__ __forceinline__ void dghost(T p, T q, T &dp, T &dq) {
     if (p >= q) {
@@ -206,17 +232,17 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return r;
 }
 
-// Adds per-ignition (x, y) contributions of this block into acc[block][2g+c].
+// Adds per-ignition (x, y) contributions of node block b into acc[b][2g+c].
 __device__ __forceinline__ void shift_reduce(int g, double cx, double cy, int nign, double *acc,
-                                             double *sh) {
+                                             double *sh, int b) {
     const int any = __syncthreads_or(g >= 0);
     if (!any) return;
     for (int k = 0; k < nign; k++) {
         const double sx = block_sum(g == k ? cx : 0.0, sh);
         const double sy = block_sum(g == k ? cy : 0.0, sh);
         if (threadIdx.x == 0) {
-            acc[(size_t)blockIdx.x * kShift + 2 * k] += sx;
-            acc[(size_t)blockIdx.x * kShift + 2 * k + 1] += sy;
+            acc[(size_t)b * kShift + 2 * k] += sx;
+            acc[(size_t)b * kShift + 2 * k + 1] += sy;
         }
     }
 }
@@ -282,11 +308,8 @@ template <typename T> __global__ void k_adj_corners(const AdjArgs a, const T *E,
 // adjoint plus the share of each side ghost extrapolated from it;
 // out = b1 + h b2 + b3 + that (null bases count as zero).
 template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_adj_ghostT(const AdjArgs a, const T *src, const T *LE, const T *b1, const T *b2, T h,
-             const T *b3, T *out) {
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= a.nx * a.ny) return;
+__device__ __forceinline__ T ghostT_node(const AdjArgs &a, const T *src, const T *LE, const T *b1,
+                                         const T *b2, T h, const T *b3, int i) {
     const int nx = a.nx, ny = a.ny;
     const int x = i % nx, y = i / nx;
     T s = LE[ext_idx(a, x, y)];
@@ -310,8 +333,26 @@ k_adj_ghostT(const AdjArgs a, const T *src, const T *LE, const T *b1, const T *b
     if (b1) s += b1[i];
     if (b2) s += h * b2[i];
     if (b3) s += b3[i];
-    out[i] = s;
+    return s;
 }
+
+template <typename T>
+__global__ void __launch_bounds__(kAB)
+k_adj_ghostT(const AdjArgs a, const T *src, const T *LE, const T *b1, const T *b2, T h,
+             const T *b3, T *out, int32_t *flag) {
+    const int i = blockIdx.x * kAB + threadIdx.x;
+    const bool in = i < a.nx * a.ny;
+    if (flag) {   // out's block flag (nonzero somewhere in the block)
+        const T o = in ? ghostT_node(a, src, LE, b1, b2, h, b3, i) : T(0);
+        if (in) out[i] = o;
+        const int any = __syncthreads_or(o != T(0));
+        if (threadIdx.x == 0) flag[blockIdx.x] = any;
+        return;
+    }
+    if (!in) return;
+    out[i] = ghostT_node(a, src, LE, b1, b2, h, b3, i);
+}
+
 
 
 // ---- fused reverse step: node values with the side ghosts of Sect. 4.1
@@ -502,25 +543,63 @@ __device__ __forceinline__ T rev3_node(const AdjArgs &a, int i, int x, int y, T 
     return T(0);
 }
 
+// The four reverse kernels below walk the node blocks (kAB nodes each) with
+// a grid stride (launched with one work-group per block): a block whose
+// flags show all-zero inputs skips its work, which is most blocks, since the
+// adjoint of a run is nonzero on a small part of the mesh.  Each block's work
+// is uniform in the block, and its barrier-separated steps end with one more
+// barrier before the next block reuses the shared array.
+
 // Part 1 of step n alone (the last step of a segment).
 template <typename T>
 __global__ void __launch_bounds__(kAB)
 k_rev_stage2(const AdjArgs a, int n, const int32_t *set_step, const T *psi_n, const T *P0,
              const T *B, const T *pn1, T *L1, T *LT, T *LP0, const T *u, const T *v,
              const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
-             const fire_ignition *ign, T *D, double *acc) {
+             const fire_ignition *ign, T *D, double *acc, AdjFlags fl) {
     __shared__ double sh[kAB];
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    int g = -1;
-    double cx = 0.0, cy = 0.0;
-    if (i < a.nx * a.ny) {
-        const int x = i % a.nx, y = i / a.nx;
-        const T l = L1[i];
-        const T lam = rev1_node(a, n, i, x, y, l, set_step, psi_n, P0, B, pn1, LT, LP0, u, v, gzx,
-                                gzy, cat, coef, ign, D, g, cx, cy);
-        if (set_step[i] == n) L1[i] = lam;
+    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
+    auto block = [&](const int b) {
+        const int i = b * kAB + threadIdx.x;
+        const bool in = i < nn;
+        if (!fl.l1[b] && !fl.lt[b]) {
+            // lam and dL/dt_i zero on the block: so is every output but
+            // stale LP0
+            if (fl.lp0[b]) {
+                if (in) LP0[i] = T(0);
+                if (threadIdx.x == 0) fl.lp0[b] = 0;
+            }
+            return;
+        }
+        int g = -1;
+        double cx = 0.0, cy = 0.0;
+        T l1 = T(0), lp0 = T(0), lt = T(0);
+        if (in) {
+            const int x = i % a.nx, y = i / a.nx;
+            l1 = L1[i];
+            const T lam = rev1_node(a, n, i, x, y, l1, set_step, psi_n, P0, B, pn1, LT, LP0, u,
+                                    v, gzx, gzy, cat, coef, ign, D, g, cx, cy);
+            if (set_step[i] == n) {
+                L1[i] = lam;
+                l1 = lam;
+            }
+            lp0 = LP0[i];
+            lt = LT[i];
+        }
+        const int f1 = __syncthreads_or(l1 != T(0));
+        const int fp = __syncthreads_or(lp0 != T(0));
+        const int ft = __syncthreads_or(lt != T(0));
+        if (threadIdx.x == 0) {
+            fl.l1[b] = f1;
+            fl.lp0[b] = fp;
+            fl.lt[b] = ft;
+        }
+        shift_reduce(g, cx, cy, a.nign, acc, sh, b);
+    };
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        block(b);
+        __syncthreads();
     }
-    shift_reduce(g, cx, cy, a.nign, acc, sh);
 }
 
 // Reverse, part 2: dL/dpsi* = dL/dpsi^{n+1}/2 + (stage-2 partials gathered
@@ -530,52 +609,86 @@ template <typename T>
 __global__ void __launch_bounds__(kAB)
 k_rev_stage1(const AdjArgs a, const T *D, const T *B, const T *L1, T *LB, const T *P0,
              const T *u, const T *v, const T *gzx, const T *gzy, const uint8_t *cat,
-             const T *coef, T *D1, double *gu, double *gv, double *gm) {
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= a.nx * a.ny) return;
-    const int x = i % a.nx, y = i / a.nx;
-    const T l1 = L1[i];
-    T lb = gather_node(a, D, L1, B, x, y);
-    lb += T(0.5) * l1;
-    LB[i] = lb;
-    if (l1 == T(0) && lb == T(0)) return;
-    // wind and multiplier partials of both stages, one update per cell:
-    // stage 2 (weight dt/2 lam^{n+1}, recomputed), then stage 1 (dt lam*)
-    double du = gu[i], dv = gv[i], dm = gm[i];
-    if (l1 != T(0)) {
-        const RhsGrad<T> r2 = stage_grad(a, B, x, y, u, v, gzx, gzy, cat, coef);
-        const T q2 = T(0.5) * T(a.dt) * l1;
-        du += (double)(q2 * r2.du);
-        dv += (double)(q2 * r2.dv);
-        dm += (double)(q2 * r2.dm);
+             const T *coef, T *D1, double *gu, double *gv, double *gm, AdjFlags fl) {
+    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
+    auto block = [&](const int b) {
+        const int i = b * kAB + threadIdx.x;
+        const bool in = i < nn;
+        if (!nbhd_flag(fl.l1, a, b)) {
+            // no lam^{n+1} within reach: dL/dpsi* is zero on the block
+            if (fl.lb[b]) {
+                if (in) LB[i] = T(0);
+                if (threadIdx.x == 0) fl.lb[b] = 0;
+            }
+            return;
+        }
+        const int x = i % a.nx, y = i / a.nx;
+        T l1 = T(0), lb = T(0);
+        if (in) {
+            l1 = L1[i];
+            lb = gather_node(a, D, L1, B, x, y);
+            lb += T(0.5) * l1;
+            LB[i] = lb;
+        }
+        const int fb = __syncthreads_or(lb != T(0));
+        if (threadIdx.x == 0) fl.lb[b] = fb;
+        if (!in || (l1 == T(0) && lb == T(0))) return;
+        // wind and multiplier partials of both stages, one update per cell:
+        // stage 2 (weight dt/2 lam^{n+1}, recomputed), then stage 1 (dt lam*)
+        double du = gu[i], dv = gv[i], dm = gm[i];
+        if (l1 != T(0)) {
+            const RhsGrad<T> r2 = stage_grad(a, B, x, y, u, v, gzx, gzy, cat, coef);
+            const T q2 = T(0.5) * T(a.dt) * l1;
+            du += (double)(q2 * r2.du);
+            dv += (double)(q2 * r2.dv);
+            dm += (double)(q2 * r2.dm);
+        }
+        if (lb != T(0)) {
+            const RhsGrad<T> r1 = stage_grad(a, P0, x, y, u, v, gzx, gzy, cat, coef);
+            const T q1 = T(a.dt) * lb;
+            stage_D(r1, i, (size_t)nn, q1, D1);
+            du += (double)(q1 * r1.du);
+            dv += (double)(q1 * r1.dv);
+            dm += (double)(q1 * r1.dm);
+        }
+        gu[i] = du;
+        gv[i] = dv;
+        gm[i] = dm;
+    };
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        block(b);
+        __syncthreads();
     }
-    if (lb != T(0)) {
-        const RhsGrad<T> r1 = stage_grad(a, P0, x, y, u, v, gzx, gzy, cat, coef);
-        const T q1 = T(a.dt) * lb;
-        stage_D(r1, i, (size_t)a.nx * a.ny, q1, D1);
-        du += (double)(q1 * r1.du);
-        dv += (double)(q1 * r1.dv);
-        dm += (double)(q1 * r1.dm);
-    }
-    gu[i] = du;
-    gv[i] = dv;
-    gm[i] = dm;
 }
 
 // Part 3 of step n alone (the first step of a segment).
 template <typename T>
 __global__ void __launch_bounds__(kAB)
 k_rev_psi(const AdjArgs a, const T *D1, const T *P0, const T *LP0, const T *LB, const T *psi_n,
-          const fire_ignition *ign, T *L1, double *acc) {
+          const fire_ignition *ign, T *L1, double *acc, AdjFlags fl) {
     __shared__ double sh[kAB];
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    int g = -1;
-    double cx = 0.0, cy = 0.0;
-    if (i < a.nx * a.ny) {
-        const int x = i % a.nx, y = i / a.nx;
-        L1[i] = rev3_node(a, i, x, y, L1[i], D1, P0, LP0, LB, psi_n, ign, g, cx, cy);
+    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
+    auto block = [&](const int b) {
+        // zero inputs (L1 and LP0 of the block, LB within reach) give zero
+        // outputs, and L1 is zero there already
+        if (!fl.l1[b] && !fl.lp0[b] && !nbhd_flag(fl.lb, a, b)) return;
+        const int i = b * kAB + threadIdx.x;
+        int g = -1;
+        double cx = 0.0, cy = 0.0;
+        T l = T(0);
+        if (i < nn) {
+            const int x = i % a.nx, y = i / a.nx;
+            l = rev3_node(a, i, x, y, L1[i], D1, P0, LP0, LB, psi_n, ign, g, cx, cy);
+            L1[i] = l;
+        }
+        const int f1 = __syncthreads_or(l != T(0));
+        if (threadIdx.x == 0) fl.l1[b] = f1;
+        shift_reduce(g, cx, cy, a.nign, acc, sh, b);
+    };
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        block(b);
+        __syncthreads();
     }
-    shift_reduce(g, cx, cy, a.nign, acc, sh);
 }
 
 // Part 3 of step n (args a3) fused with part 1 of step n - 1 (args a1) at
@@ -586,21 +699,43 @@ k_rev_psi_stage2(const AdjArgs a3, const AdjArgs a1, int n1, const T *D1, const 
                  T *LP0, const T *LB, const T *psi_n, const int32_t *set_step,
                  const T *psi_n1, const T *P0n1, const T *Bn1, T *L1, T *LT, const T *u,
                  const T *v, const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
-                 const fire_ignition *ign, T *D, double *acc) {
+                 const fire_ignition *ign, T *D, double *acc, AdjFlags fl) {
     __shared__ double sh[kAB];
-    const int i = blockIdx.x * kAB + threadIdx.x;
-    int g3 = -1, g1 = -1;
-    double cx3 = 0.0, cy3 = 0.0, cx1 = 0.0, cy1 = 0.0;
-    if (i < a3.nx * a3.ny) {
-        const int x = i % a3.nx, y = i / a3.nx;
-        // step n: dL/dpsi^n (psi^n is the state after step n - 1)
-        const T l = rev3_node(a3, i, x, y, L1[i], D1, P0n, LP0, LB, psi_n, ign, g3, cx3, cy3);
-        // step n - 1, whose output psi^n is psi_n
-        L1[i] = rev1_node(a1, n1, i, x, y, l, set_step, psi_n1, P0n1, Bn1, psi_n, LT, LP0, u, v,
-                          gzx, gzy, cat, coef, ign, D, g1, cx1, cy1);
+    const int nn = a3.nx * a3.ny, nb = (nn + kAB - 1) / kAB;
+    auto block = [&](const int b) {
+        // zero inputs of both parts (L1, LP0 and LT of the block, LB within
+        // reach) give zero outputs, which the block holds already
+        if (!fl.l1[b] && !fl.lp0[b] && !fl.lt[b] && !nbhd_flag(fl.lb, a3, b)) return;
+        const int i = b * kAB + threadIdx.x;
+        int g3 = -1, g1 = -1;
+        double cx3 = 0.0, cy3 = 0.0, cx1 = 0.0, cy1 = 0.0;
+        T l1 = T(0), lp0 = T(0), lt = T(0);
+        if (i < nn) {
+            const int x = i % a3.nx, y = i / a3.nx;
+            // step n: dL/dpsi^n (psi^n is the state after step n - 1)
+            const T l = rev3_node(a3, i, x, y, L1[i], D1, P0n, LP0, LB, psi_n, ign, g3, cx3, cy3);
+            // step n - 1, whose output psi^n is psi_n
+            l1 = rev1_node(a1, n1, i, x, y, l, set_step, psi_n1, P0n1, Bn1, psi_n, LT, LP0, u, v,
+                           gzx, gzy, cat, coef, ign, D, g1, cx1, cy1);
+            L1[i] = l1;
+            lp0 = LP0[i];
+            lt = LT[i];
+        }
+        const int f1 = __syncthreads_or(l1 != T(0));
+        const int fp = __syncthreads_or(lp0 != T(0));
+        const int ft = __syncthreads_or(lt != T(0));
+        if (threadIdx.x == 0) {
+            fl.l1[b] = f1;
+            fl.lp0[b] = fp;
+            fl.lt[b] = ft;
+        }
+        shift_reduce(g3, cx3, cy3, a3.nign, acc, sh, b);
+        shift_reduce(g1, cx1, cy1, a1.nign, acc, sh, b);
+    };
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        block(b);
+        __syncthreads();
     }
-    shift_reduce(g3, cx3, cy3, a3.nign, acc, sh);
-    shift_reduce(g1, cx1, cy1, a1.nign, acc, sh);
 }
 
 // Node times t^ on the extended mesh: t' where psi >= 0 and on the ghosts,
@@ -663,11 +798,16 @@ k_adj_frac(const AdjArgs a, const T *E, const T *TH, const T *lamF, const uint8_
 // dL/dt_i from dL/dt^ where t^ = t_i (psi < 0).
 template <typename T>
 __global__ void __launch_bounds__(kAB)
-k_lt_init(const AdjArgs a, const T *psi, const T *LTH, T *LT) {
+k_lt_init(const AdjArgs a, const T *psi, const T *LTH, T *LT, int32_t *flag) {
     const int i = blockIdx.x * kAB + threadIdx.x;
-    if (i >= a.nx * a.ny) return;
-    const int x = i % a.nx, y = i / a.nx;
-    LT[i] = psi[i] < T(0) ? LTH[ext_idx(a, x, y)] : T(0);
+    T lt = T(0);
+    if (i < a.nx * a.ny) {
+        const int x = i % a.nx, y = i / a.nx;
+        lt = psi[i] < T(0) ? LTH[ext_idx(a, x, y)] : T(0);
+        LT[i] = lt;
+    }
+    const int any = __syncthreads_or(lt != T(0));
+    if (threadIdx.x == 0) flag[blockIdx.x] = any;
 }
 
 template <typename T> __global__ void __launch_bounds__(kAB) k_set(T *p, T v, size_t cnt) {
@@ -716,7 +856,7 @@ int hip_fail(hipError_t e) { return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP; }
 
 struct AdjLayout {
     size_t ckpt, stack, rp0, rb, set_step, flux, e1, e2, le, th, l1, lt, lp0,
-        lb, d, d1, gu, gv, gm, acc, part, small, total;
+        lb, d, d1, gu, gv, gm, acc, part, small, flags, total;
 };
 
 }  // namespace
@@ -772,6 +912,7 @@ AdjLayout adj_layout(const fire_mesh *m, int ncat, int nsteps, int every) {
     take(L.acc, nblk * kShift * 8);
     take(L.part, nblk * (size_t)(ncat > kShift ? ncat : kShift) * 8);
     take(L.small, (size_t)(256 + kShift) * 8);
+    take(L.flags, 4 * nblk * sizeof(int32_t));   // AdjFlags: l1, lb, lp0, lt
     L.total = o;
     return L;
 }
@@ -795,6 +936,11 @@ template <typename T> struct Run {
     }
     const T *cur_psi() { return reinterpret_cast<const T *>(c->arena + c->off_psi[c->cur]); }
     const T *tign_final() { return reinterpret_cast<const T *>(c->arena + c->off_tign); }
+    AdjFlags flags() {
+        int32_t *f = at<int32_t>(A->L.flags);
+        const size_t nb = (n + kAB - 1) / kAB;
+        return AdjFlags{f, f + nb, f + 2 * nb, f + 3 * nb};
+    }
     // whether any ignition is active at time t (the test of ign_setup)
     int ign_active_at(double t) const {
         for (int g = 0; g < c->nign; g++) {
@@ -844,11 +990,16 @@ template <typename T> struct Run {
                            arr(A->L.th), dF, c->cat, coef(), tp, arr(A->L.le), arr(A->L.e2));
         hipLaunchKernelGGL(k_adj_corners<T>, dim3(1), dim3(64), 0, s, a, arr(A->L.e1),
                            arr(A->L.le));
+        const AdjFlags fl = flags();
         hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, psiN, arr(A->L.le),
                            (const T *)nullptr, (const T *)nullptr, T(0), (const T *)nullptr,
-                           arr(A->L.l1));
+                           arr(A->L.l1), fl.l1);
         hipLaunchKernelGGL(k_lt_init<T>, dim3(gn), dim3(kAB), 0, s, a, psiN, arr(A->L.e2),
-                           arr(A->L.lt));
+                           arr(A->L.lt), fl.lt);
+        // LB and LP0 hold whatever the arena held: flagged, so a block that
+        // skips its work clears them
+        hipLaunchKernelGGL(k_set<int32_t>, dim3(gn), dim3(kAB), 0, s, fl.lb, 1, (size_t)gn);
+        hipLaunchKernelGGL(k_set<int32_t>, dim3(gn), dim3(kAB), 0, s, fl.lp0, 1, (size_t)gn);
         return hipGetLastError();
     }
 
@@ -879,30 +1030,34 @@ template <typename T> struct Run {
         double *gu = at<double>(A->L.gu), *gv = at<double>(A->L.gv), *gm = at<double>(A->L.gm);
         double *acc = at<double>(A->L.acc);
         const int32_t *set_step = at<int32_t>(A->L.set_step);
+        const AdjFlags fl = flags();
+        // one work-group per node block: walking several blocks per
+        // work-group measured slower (each skip still waits for its flags)
+        const int rg = gn;
         AdjArgs an = a;
         an.t = A->tstep[s1 - 1];
         an.ign_active = ign_active_at(an.t);
         int k = s1 - 1 - s0;
-        hipLaunchKernelGGL(k_rev_stage2<T>, dim3(gn), dim3(kAB), 0, s, an, s1 - 1, set_step,
+        hipLaunchKernelGGL(k_rev_stage2<T>, dim3(rg), dim3(kAB), 0, s, an, s1 - 1, set_step,
                            stack(k), rp0(k), rb(k), stack(k + 1), L1, LT, LP0, u, v, gx, gy,
-                           c->cat, coef(), ign(), D, acc);
+                           c->cat, coef(), ign(), D, acc, fl);
         for (int n_ = s1 - 1; n_ >= s0; n_--) {
             k = n_ - s0;
             an.t = A->tstep[n_];
             an.ign_active = ign_active_at(an.t);
-            hipLaunchKernelGGL(k_rev_stage1<T>, dim3(gn), dim3(kAB), 0, s, an, D, rb(k), L1, LB,
-                               rp0(k), u, v, gx, gy, c->cat, coef(), D1, gu, gv, gm);
+            hipLaunchKernelGGL(k_rev_stage1<T>, dim3(rg), dim3(kAB), 0, s, an, D, rb(k), L1, LB,
+                               rp0(k), u, v, gx, gy, c->cat, coef(), D1, gu, gv, gm, fl);
             if (n_ > s0) {
                 AdjArgs ap = a;
                 ap.t = A->tstep[n_ - 1];
                 ap.ign_active = ign_active_at(ap.t);
-                hipLaunchKernelGGL(k_rev_psi_stage2<T>, dim3(gn), dim3(kAB), 0, s, an, ap,
+                hipLaunchKernelGGL(k_rev_psi_stage2<T>, dim3(rg), dim3(kAB), 0, s, an, ap,
                                    n_ - 1, D1, rp0(k), LP0, LB, stack(k), set_step, stack(k - 1),
                                    rp0(k - 1), rb(k - 1), L1, LT, u, v, gx, gy, c->cat, coef(),
-                                   ign(), D, acc);
+                                   ign(), D, acc, fl);
             } else {
-                hipLaunchKernelGGL(k_rev_psi<T>, dim3(gn), dim3(kAB), 0, s, an, D1, rp0(k), LP0,
-                                   LB, stack(k), ign(), L1, acc);
+                hipLaunchKernelGGL(k_rev_psi<T>, dim3(rg), dim3(kAB), 0, s, an, D1, rp0(k), LP0,
+                                   LB, stack(k), ign(), L1, acc, fl);
             }
         }
         return hipGetLastError();

@@ -337,11 +337,15 @@ typedef struct fire_adj fire_adj;
 
 /* Bytes of caller-owned device scratch for a differentiable run of nsteps
  * steps with a checkpoint every `every` steps: about
- * (nsteps/every + every + 24) x nx x ny elements.  0 if invalid. */
+ * (nsteps/every + 6 every + 26) x nx x ny elements (two sets of replay
+ * buffers, so one segment is replayed while the next is reversed).  0 if
+ * invalid. */
 size_t fire_adj_bytes(const fire_mesh *mesh, int32_t ncat, int32_t nsteps, int32_t every);
 
 /* Attach to a context (which must outlive the handle); scratch is device
- * memory of fire_adj_bytes(), 256-byte aligned. */
+ * memory of fire_adj_bytes(), 256-byte aligned.  Creates one stream (default
+ * priority) and five events for the backward pass; FIRE_ERR_HIP if that
+ * fails. */
 int fire_adj_init(fire_adj **out, fire_ctx *ctx, int32_t nsteps, int32_t every, void *scratch,
                   size_t scratch_bytes);
 
@@ -355,11 +359,12 @@ int fire_adj_forward(fire_adj *a, const void *u, const void *v, double dt);
  * (device [ny][nx], context dtype), grad_mult (host double[ncat]) and, if not
  * NULL, grad_shift (host double[2 nign], x then y per ignition).  The context
  * must not have been stepped since fire_adj_forward (FIRE_ERR_STATE).
- * Waits for the stream. */
+ * Segment replays run on the handle's own stream, ordered by events against
+ * the context's stream, which does the rest.  Waits for both. */
 int fire_adj_backward(fire_adj *a, const void *dF, void *grad_u, void *grad_v,
                       double *grad_mult, double *grad_shift);
 
-/* Releases the handle (host memory only). */
+/* Releases the handle, its stream and events (waits for its stream). */
 void fire_adj_destroy(fire_adj *a);
 
 /* ------------------------------------------------------------------------

@@ -55,29 +55,33 @@ __device__ __forceinline__ int ext_idx(const AdjArgs &a, int x, int y) {
     return (y + 1) * (a.nx + 2) + (x + 1);
 }
 
-// Per-block flags of the reverse pass (block b = nodes b kAB .. b kAB + kAB - 1):
-// nonzero where the block's values of dL/dpsi^{n+1} (L1), dL/dpsi* (LB),
-// the crossing part of dL/dpsi' (LP0) or dL/dt_i (LT) may be nonzero.  The
-// adjoint of a run is nonzero only where the final fuel fraction depends on
-// the state, a region that shrinks towards the ignitions as the steps are
-// reversed; a block whose inputs are all zero has all-zero outputs, so it
-// skips its work and writes only the zeros that stale values need.
+// The reverse step works on tiles of kRTX x kRTY nodes (one work-group of
+// kAB threads, two nodes each).  Per-tile flags record where an array may be
+// nonzero: dL/dpsi^{n+1} (two buffers, l1[0] / l1[1]), the crossing part of
+// dL/dpsi' (lp0) and dL/dt_i (lt).  The adjoint of a run is nonzero only
+// where the final fuel fraction depends on the state, a small part of the
+// mesh; a tile whose inputs within reach are all zero has all-zero outputs,
+// so it skips its work and only clears stale values.
+constexpr int kRTX = 32, kRTY = 16;
+constexpr int kREX = kRTX + 2, kREY = kRTY + 2;   // the tile and one ring
 struct AdjFlags {
-    int32_t *l1, *lb, *lp0, *lt;
+    int32_t *l1[2], *lp0, *lt;
 };
 
-// Whether any block holding a node within one row or column of block b's
-// nodes (the reach of the stencil gathers, the ghost transposes included)
-// has its flag set.
-__device__ __forceinline__ bool nbhd_flag(const int32_t *f, const AdjArgs &a, int b) {
-    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
-    const int lo = b * kAB, hi = min(lo + kAB, nn) - 1;
-    auto blk = [&](int i) { return (i < 0 || i >= nn) ? -1 : i / kAB; };
-    const int c[7] = {b - 1, b, b + 1, blk(lo - a.nx), blk(hi - a.nx), blk(lo + a.nx),
-                      blk(hi + a.nx)};
+__device__ __forceinline__ int rtiles_x(const AdjArgs &a) { return (a.nx + kRTX - 1) / kRTX; }
+__device__ __forceinline__ int rtiles_y(const AdjArgs &a) { return (a.ny + kRTY - 1) / kRTY; }
+
+// Whether tile t or one of its eight neighbours has its flag set (the
+// reach of the ring's gathers, the ghost transposes included).
+__device__ __forceinline__ bool nbhd_flag(const int32_t *f, const AdjArgs &a, int t) {
+    const int tx = rtiles_x(a), ty = rtiles_y(a);
+    const int cx = t % tx, cy = t / tx;
     bool any = false;
-    for (int k = 0; k < 7; k++)
-        if (c[k] >= 0 && c[k] < nb && f[c[k]]) any = true;
+    for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+            const int x = cx + dx, y = cy + dy;
+            if (x >= 0 && x < tx && y >= 0 && y < ty && f[y * tx + x]) any = true;
+        }
     return any;
 }
 
@@ -232,7 +236,43 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return r;
 }
 
-// Adds per-ignition (x, y) contributions of node block b into acc[b][2g+c].
+// Threads of the reversed-step kernel: one per node of the tile and its
+// ring (kREX kREY = 612 of them), in ten waves.
+constexpr int kRT = 640;
+
+// Fixed-order sum over the kRT threads of a block (every thread gets it):
+// threads 512.. fold onto 0..127, then a halving tree.
+__device__ __forceinline__ double block_sum_rt(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    if (t < kRT - 512) sh[t] += sh[t + 512];
+    __syncthreads();
+    for (int s = 256; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// shift_reduce over the kRT threads of a reversed-step block.
+__device__ __forceinline__ void shift_reduce_rt(int g, double cx, double cy, int nign,
+                                                double *acc, double *sh, int b) {
+    const int any = __syncthreads_or(g >= 0);
+    if (!any) return;
+    for (int k = 0; k < nign; k++) {
+        const double sx = block_sum_rt(g == k ? cx : 0.0, sh);
+        const double sy = block_sum_rt(g == k ? cy : 0.0, sh);
+        if (threadIdx.x == 0) {
+            acc[(size_t)b * kShift + 2 * k] += sx;
+            acc[(size_t)b * kShift + 2 * k + 1] += sy;
+        }
+    }
+}
+
+// Adds per-ignition (x, y) contributions of tile b into acc[b][2g+c].
 __device__ __forceinline__ void shift_reduce(int g, double cx, double cy, int nign, double *acc,
                                              double *sh, int b) {
     const int any = __syncthreads_or(g >= 0);
@@ -339,17 +379,9 @@ __device__ __forceinline__ T ghostT_node(const AdjArgs &a, const T *src, const T
 template <typename T>
 __global__ void __launch_bounds__(kAB)
 k_adj_ghostT(const AdjArgs a, const T *src, const T *LE, const T *b1, const T *b2, T h,
-             const T *b3, T *out, int32_t *flag) {
+             const T *b3, T *out) {
     const int i = blockIdx.x * kAB + threadIdx.x;
-    const bool in = i < a.nx * a.ny;
-    if (flag) {   // out's block flag (nonzero somewhere in the block)
-        const T o = in ? ghostT_node(a, src, LE, b1, b2, h, b3, i) : T(0);
-        if (in) out[i] = o;
-        const int any = __syncthreads_or(o != T(0));
-        if (threadIdx.x == 0) flag[blockIdx.x] = any;
-        return;
-    }
-    if (!in) return;
+    if (i >= a.nx * a.ny) return;
     out[i] = ghostT_node(a, src, LE, b1, b2, h, b3, i);
 }
 
@@ -512,19 +544,59 @@ __device__ __forceinline__ T rev1_node(const AdjArgs &a, int n, int i, int x, in
     return lam;
 }
 
-// Reverse, part 3 at node i for step n: dL/dpsi' = crossing part +
-// dL/dpsi^{n+1}/2 + dL/dpsi* + (stage-1 partials gathered through the ghosts
-// of psi'), then through the ignition minimum: returns dL/dpsi^n (zero where
-// an ignition set psi', whose shift gets the contribution instead).
+// Sum of the stage-1 partials aimed at owned node (x, y), from the tile's
+// LDS copy of dL/dpsi* (W) and of the partial planes (Dc, Dw, De, Ds, Dn) on
+// the tile and its ring, plus its share of the side ghosts extrapolated from
+// it: gather_node in the same order of terms.  (ex, ey) is the node's
+// position in the ringed tile; P (psi') comes from memory for the ghost
+// formula.
 template <typename T>
-__device__ __forceinline__ T rev3_node(const AdjArgs &a, int i, int x, int y, T l1, const T *D1,
-                                       const T *P0, const T *LP0, const T *LB, const T *psi_n,
-                                       const fire_ignition *ign, int &g, double &cx,
-                                       double &cy) {
-    T l = gather_node(a, D1, LB, P0, x, y);
+__device__ __forceinline__ T gather_lds(const AdjArgs &a, const T (*W)[kREX],
+                                        const T (*Dp)[kREY][kREX], const T *P, int x, int y,
+                                        int ex, int ey, int x0, int y0) {
+    const int nx = a.nx, ny = a.ny;
+    T s = T(0);
+    if (W[ey][ex] != T(0)) s += Dp[0][ey][ex];
+    if (x + 1 < nx && W[ey][ex + 1] != T(0)) s += Dp[1][ey][ex + 1];
+    if (x - 1 >= 0 && W[ey][ex - 1] != T(0)) s += Dp[2][ey][ex - 1];
+    if (y + 1 < ny && W[ey + 1][ex] != T(0)) s += Dp[3][ey + 1][ex];
+    if (y - 1 >= 0 && W[ey - 1][ex] != T(0)) s += Dp[4][ey - 1][ex];
+    // the ghost sources sit in the ring: columns 0 / nx - 1, rows 0 / ny - 1
+    const int gx0 = 0 - x0 + 1, gx1 = nx - 1 - x0 + 1;
+    const int gy0 = 0 - y0 + 1, gy1 = ny - 1 - y0 + 1;
+    T dp, dq;
+    if (x <= 1 && W[ey][gx0] != T(0)) {
+        dghost(P[y * nx], P[y * nx + 1], dp, dq);
+        s += Dp[1][ey][gx0] * (x == 0 ? dp : dq);
+    }
+    if (x >= nx - 2 && W[ey][gx1] != T(0)) {
+        dghost(P[y * nx + nx - 1], P[y * nx + nx - 2], dp, dq);
+        s += Dp[2][ey][gx1] * (x == nx - 1 ? dp : dq);
+    }
+    if (y <= 1 && W[gy0][ex] != T(0)) {
+        dghost(P[x], P[nx + x], dp, dq);
+        s += Dp[3][gy0][ex] * (y == 0 ? dp : dq);
+    }
+    if (y >= ny - 2 && W[gy1][ex] != T(0)) {
+        dghost(P[(ny - 1) * nx + x], P[(ny - 2) * nx + x], dp, dq);
+        s += Dp[4][gy1][ex] * (y == ny - 1 ? dp : dq);
+    }
+    return s;
+}
+
+// Reverse, part 3 at owned node i for step n, given the gathered stage-1
+// partials (gath) and dL/dpsi* (lb): dL/dpsi' = gathered partials + crossing part +
+// dL/dpsi^{n+1}/2 + dL/dpsi*, then through the ignition minimum: returns
+// dL/dpsi^n (zero where an ignition set psi', whose shift gets the
+// contribution instead).
+template <typename T>
+__device__ __forceinline__ T rev3_lds(const AdjArgs &a, int i, int x, int y, T l1, T lb, T gath,
+                                      const T *LP0, const T *psi_n, const fire_ignition *ign,
+                                      int &g, double &cx, double &cy) {
+    T l = gath;
     l += LP0[i];
     l += T(0.5) * l1;
-    l += LB[i];
+    l += lb;
     int sg = -1, tg;
     if (a.ign_active) ignite_node(a, ign, psi_n[i], x, y, sg, tg);
     if (sg < 0) return l;
@@ -543,199 +615,194 @@ __device__ __forceinline__ T rev3_node(const AdjArgs &a, int i, int x, int y, T 
     return T(0);
 }
 
-// The four reverse kernels below walk the node blocks (kAB nodes each) with
-// a grid stride (launched with one work-group per block): a block whose
-// flags show all-zero inputs skips its work, which is most blocks, since the
-// adjoint of a run is nonzero on a small part of the mesh.  Each block's work
-// is uniform in the block, and its barrier-separated steps end with one more
-// barrier before the next block reuses the shared array.
-
-// Part 1 of step n alone (the last step of a segment).
+// Part 1 alone of step n (the last step of a segment), tile by tile:
+// dL/dpsi^{n+1} in L1 gets the crossing part of the nodes set in the step,
+// the stage-2 partials go to D, LP0 and LT are updated.
 template <typename T>
 __global__ void __launch_bounds__(kAB)
-k_rev_stage2(const AdjArgs a, int n, const int32_t *set_step, const T *psi_n, const T *P0,
-             const T *B, const T *pn1, T *L1, T *LT, T *LP0, const T *u, const T *v,
-             const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
-             const fire_ignition *ign, T *D, double *acc, AdjFlags fl) {
+k_rev_part1(const AdjArgs a, int n, const int32_t *set_step, const T *psi_n, const T *P0,
+            const T *B, const T *pn1, T *L1, int32_t *f_l1, T *LT, T *LP0, const T *u,
+            const T *v, const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
+            const fire_ignition *ign, T *D, double *acc, AdjFlags fl) {
     __shared__ double sh[kAB];
-    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
-    auto block = [&](const int b) {
-        const int i = b * kAB + threadIdx.x;
-        const bool in = i < nn;
-        if (!fl.l1[b] && !fl.lt[b]) {
-            // lam and dL/dt_i zero on the block: so is every output but
-            // stale LP0
-            if (fl.lp0[b]) {
-                if (in) LP0[i] = T(0);
-                if (threadIdx.x == 0) fl.lp0[b] = 0;
+    const int t = blockIdx.x;
+    const int x0 = (t % rtiles_x(a)) * kRTX, y0 = (t / rtiles_x(a)) * kRTY;
+    if (!f_l1[t] && !fl.lt[t]) {
+        // lam and dL/dt_i zero on the tile: so is every output but stale LP0
+        if (fl.lp0[t]) {
+            for (int j = 0; j < 2; j++) {
+                const int q = threadIdx.x + j * kAB;
+                const int x = x0 + q % kRTX, y = y0 + q / kRTX;
+                if (x < a.nx && y < a.ny) LP0[y * a.nx + x] = T(0);
             }
-            return;
+            if (threadIdx.x == 0) fl.lp0[t] = 0;
         }
+        return;
+    }
+    bool n1 = false, np = false, nt = false;
+    for (int j = 0; j < 2; j++) {
+        const int q = threadIdx.x + j * kAB;
+        const int x = x0 + q % kRTX, y = y0 + q / kRTX;
         int g = -1;
         double cx = 0.0, cy = 0.0;
-        T l1 = T(0), lp0 = T(0), lt = T(0);
-        if (in) {
-            const int x = i % a.nx, y = i / a.nx;
-            l1 = L1[i];
+        if (x < a.nx && y < a.ny) {
+            const int i = y * a.nx + x;
+            T l1 = L1[i];
             const T lam = rev1_node(a, n, i, x, y, l1, set_step, psi_n, P0, B, pn1, LT, LP0, u,
                                     v, gzx, gzy, cat, coef, ign, D, g, cx, cy);
             if (set_step[i] == n) {
                 L1[i] = lam;
                 l1 = lam;
             }
-            lp0 = LP0[i];
-            lt = LT[i];
+            n1 |= l1 != T(0);
+            np |= LP0[i] != T(0);
+            nt |= LT[i] != T(0);
         }
-        const int f1 = __syncthreads_or(l1 != T(0));
-        const int fp = __syncthreads_or(lp0 != T(0));
-        const int ft = __syncthreads_or(lt != T(0));
-        if (threadIdx.x == 0) {
-            fl.l1[b] = f1;
-            fl.lp0[b] = fp;
-            fl.lt[b] = ft;
-        }
-        shift_reduce(g, cx, cy, a.nign, acc, sh, b);
-    };
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        block(b);
-        __syncthreads();
+        shift_reduce(g, cx, cy, a.nign, acc, sh, t);
+    }
+    const int f1 = __syncthreads_or(n1);
+    const int fp = __syncthreads_or(np);
+    const int ft = __syncthreads_or(nt);
+    if (threadIdx.x == 0) {
+        f_l1[t] = f1;
+        fl.lp0[t] = fp;
+        fl.lt[t] = ft;
     }
 }
 
-// Reverse, part 2: dL/dpsi* = dL/dpsi^{n+1}/2 + (stage-2 partials gathered
-// through the ghosts of psi*), then the stage-1 partials weighted by
-// dt dL/dpsi*.
+// One reversed step n, tile by tile: part 2 (dL/dpsi* = dL/dpsi^{n+1}/2 +
+// the stage-2 partials gathered through the ghosts of psi*, then the stage-1
+// partials weighted by dt dL/dpsi*, with the wind and multiplier partials of
+// both stages) on the tile and its ring into LDS, then part 3 (the gather of
+// the stage-1 partials and the ignition minimum) on the tile, and, with
+// part1, part 1 of step n - 1 at the same nodes.  Reads dL/dpsi^{n+1} from
+// L1i and the stage-2 partials from Di; writes dL/dpsi^n (part 1 of step
+// n - 1 applied) to L1o and that step's stage-2 partials to Do: the ring
+// reads its neighbours' inputs, so those two are double-buffered.
 template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_rev_stage1(const AdjArgs a, const T *D, const T *B, const T *L1, T *LB, const T *P0,
-             const T *u, const T *v, const T *gzx, const T *gzy, const uint8_t *cat,
-             const T *coef, T *D1, double *gu, double *gv, double *gm, AdjFlags fl) {
-    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
-    auto block = [&](const int b) {
-        const int i = b * kAB + threadIdx.x;
-        const bool in = i < nn;
-        if (!nbhd_flag(fl.l1, a, b)) {
-            // no lam^{n+1} within reach: dL/dpsi* is zero on the block
-            if (fl.lb[b]) {
-                if (in) LB[i] = T(0);
-                if (threadIdx.x == 0) fl.lb[b] = 0;
+__global__ void __launch_bounds__(kRT)
+k_rev_tile(const AdjArgs a2, const AdjArgs a1, int part1, int n1, const T *Di, const T *L1i,
+           const int32_t *f_l1i, const T *B, const T *P0, const T *psi_n, T *LP0, T *L1o,
+           int32_t *f_l1o, T *Do, const int32_t *set_step, const T *psi_n1, const T *P0n1,
+           const T *Bn1, T *LT, const T *u, const T *v, const T *gzx, const T *gzy,
+           const uint8_t *cat, const T *coef, const fire_ignition *ign, double *gu, double *gv,
+           double *gm, double *acc, AdjFlags fl) {
+    __shared__ T W[kREY][kREX];          // dL/dpsi* on the tile and its ring
+    __shared__ T Dp[5][kREY][kREX];      // its stage-1 partials (c, w, e, s, n)
+    __shared__ double sh[kRT];
+    const AdjArgs &a = a2;
+    const int nx = a.nx, ny = a.ny;
+    const int t = blockIdx.x;
+    const int x0 = (t % rtiles_x(a)) * kRTX, y0 = (t / rtiles_x(a)) * kRTY;
+    const bool live = nbhd_flag(f_l1i, a, t) || fl.lp0[t] || (part1 && fl.lt[t]);
+    if (!live) {
+        // every output is zero: clear what the output buffer holds from two
+        // steps ago
+        if (f_l1o[t]) {
+            const int q = threadIdx.x;
+            const int x = x0 + q % kRTX, y = y0 + q / kRTX;
+            if (q < kRTX * kRTY && x < nx && y < ny) L1o[y * nx + x] = T(0);
+            if (threadIdx.x == 0) f_l1o[t] = 0;
+        }
+        return;
+    }
+    // ---- part 2 on the tile and its ring, one node per thread
+    const int e = threadIdx.x;
+    const int ex2 = e % kREX, ey2 = e / kREX;
+    const int x2 = x0 - 1 + ex2, y2 = y0 - 1 + ey2;
+    if (e < kREX * kREY && x2 >= 0 && x2 < nx && y2 >= 0 && y2 < ny) {
+        const int ex = ex2, ey = ey2, x = x2, y = y2;
+        const int i = y * nx + x;
+        const T l1 = L1i[i];
+        T lb = gather_node(a, Di, L1i, B, x, y);
+        lb += T(0.5) * l1;
+        W[ey][ex] = lb;
+        const bool own = ex >= 1 && ex <= kRTX && ey >= 1 && ey <= kRTY;
+        double du = 0.0, dv = 0.0, dm = 0.0;
+        if (l1 != T(0) || lb != T(0)) {
+            if (own) {
+                du = gu[i];
+                dv = gv[i];
+                dm = gm[i];
             }
-            return;
+            if (own && l1 != T(0)) {
+                // wind and multiplier partials of stage 2 (weight dt/2 lam^{n+1})
+                const RhsGrad<T> r2 = stage_grad(a, B, x, y, u, v, gzx, gzy, cat, coef);
+                const T q2 = T(0.5) * T(a.dt) * l1;
+                du += (double)(q2 * r2.du);
+                dv += (double)(q2 * r2.dv);
+                dm += (double)(q2 * r2.dm);
+            }
+            if (lb != T(0)) {
+                const RhsGrad<T> r1 = stage_grad(a, P0, x, y, u, v, gzx, gzy, cat, coef);
+                const T q1 = T(a.dt) * lb;
+                Dp[0][ey][ex] = q1 * r1.dc;
+                Dp[1][ey][ex] = q1 * r1.dw;
+                Dp[2][ey][ex] = q1 * r1.de;
+                Dp[3][ey][ex] = q1 * r1.ds;
+                Dp[4][ey][ex] = q1 * r1.dn;
+                if (own) {
+                    du += (double)(q1 * r1.du);
+                    dv += (double)(q1 * r1.dv);
+                    dm += (double)(q1 * r1.dm);
+                }
+            }
+            if (own) {
+                gu[i] = du;
+                gv[i] = dv;
+                gm[i] = dm;
+            }
         }
-        const int x = i % a.nx, y = i / a.nx;
-        T l1 = T(0), lb = T(0);
-        if (in) {
-            l1 = L1[i];
-            lb = gather_node(a, D, L1, B, x, y);
-            lb += T(0.5) * l1;
-            LB[i] = lb;
-        }
-        const int fb = __syncthreads_or(lb != T(0));
-        if (threadIdx.x == 0) fl.lb[b] = fb;
-        if (!in || (l1 == T(0) && lb == T(0))) return;
-        // wind and multiplier partials of both stages, one update per cell:
-        // stage 2 (weight dt/2 lam^{n+1}, recomputed), then stage 1 (dt lam*)
-        double du = gu[i], dv = gv[i], dm = gm[i];
-        if (l1 != T(0)) {
-            const RhsGrad<T> r2 = stage_grad(a, B, x, y, u, v, gzx, gzy, cat, coef);
-            const T q2 = T(0.5) * T(a.dt) * l1;
-            du += (double)(q2 * r2.du);
-            dv += (double)(q2 * r2.dv);
-            dm += (double)(q2 * r2.dm);
-        }
-        if (lb != T(0)) {
-            const RhsGrad<T> r1 = stage_grad(a, P0, x, y, u, v, gzx, gzy, cat, coef);
-            const T q1 = T(a.dt) * lb;
-            stage_D(r1, i, (size_t)nn, q1, D1);
-            du += (double)(q1 * r1.du);
-            dv += (double)(q1 * r1.dv);
-            dm += (double)(q1 * r1.dm);
-        }
-        gu[i] = du;
-        gv[i] = dv;
-        gm[i] = dm;
-    };
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        block(b);
-        __syncthreads();
     }
-}
-
-// Part 3 of step n alone (the first step of a segment).
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_rev_psi(const AdjArgs a, const T *D1, const T *P0, const T *LP0, const T *LB, const T *psi_n,
-          const fire_ignition *ign, T *L1, double *acc, AdjFlags fl) {
-    __shared__ double sh[kAB];
-    const int nn = a.nx * a.ny, nb = (nn + kAB - 1) / kAB;
-    auto block = [&](const int b) {
-        // zero inputs (L1 and LP0 of the block, LB within reach) give zero
-        // outputs, and L1 is zero there already
-        if (!fl.l1[b] && !fl.lp0[b] && !nbhd_flag(fl.lb, a, b)) return;
-        const int i = b * kAB + threadIdx.x;
-        int g = -1;
-        double cx = 0.0, cy = 0.0;
-        T l = T(0);
-        if (i < nn) {
-            const int x = i % a.nx, y = i / a.nx;
-            l = rev3_node(a, i, x, y, L1[i], D1, P0, LP0, LB, psi_n, ign, g, cx, cy);
-            L1[i] = l;
-        }
-        const int f1 = __syncthreads_or(l != T(0));
-        if (threadIdx.x == 0) fl.l1[b] = f1;
-        shift_reduce(g, cx, cy, a.nign, acc, sh, b);
-    };
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        block(b);
-        __syncthreads();
-    }
-}
-
-// Part 3 of step n (args a3) fused with part 1 of step n - 1 (args a1) at
-// the same node: both are per-node given the gathers' inputs.
-template <typename T>
-__global__ void __launch_bounds__(kAB)
-k_rev_psi_stage2(const AdjArgs a3, const AdjArgs a1, int n1, const T *D1, const T *P0n,
-                 T *LP0, const T *LB, const T *psi_n, const int32_t *set_step,
-                 const T *psi_n1, const T *P0n1, const T *Bn1, T *L1, T *LT, const T *u,
-                 const T *v, const T *gzx, const T *gzy, const uint8_t *cat, const T *coef,
-                 const fire_ignition *ign, T *D, double *acc, AdjFlags fl) {
-    __shared__ double sh[kAB];
-    const int nn = a3.nx * a3.ny, nb = (nn + kAB - 1) / kAB;
-    auto block = [&](const int b) {
-        // zero inputs of both parts (L1, LP0 and LT of the block, LB within
-        // reach) give zero outputs, which the block holds already
-        if (!fl.l1[b] && !fl.lp0[b] && !fl.lt[b] && !nbhd_flag(fl.lb, a3, b)) return;
-        const int i = b * kAB + threadIdx.x;
+    __syncthreads();
+    // ---- part 3 of step n, then part 1 of step n - 1, one tile node per thread
+    bool nz1 = false, nzp = false, nzt = false;
+    {
+        const int q = threadIdx.x;
+        const int ex = q % kRTX + 1, ey = q / kRTX + 1;
+        const int x = x0 + ex - 1, y = y0 + ey - 1;
         int g3 = -1, g1 = -1;
         double cx3 = 0.0, cy3 = 0.0, cx1 = 0.0, cy1 = 0.0;
-        T l1 = T(0), lp0 = T(0), lt = T(0);
-        if (i < nn) {
-            const int x = i % a3.nx, y = i / a3.nx;
-            // step n: dL/dpsi^n (psi^n is the state after step n - 1)
-            const T l = rev3_node(a3, i, x, y, L1[i], D1, P0n, LP0, LB, psi_n, ign, g3, cx3, cy3);
-            // step n - 1, whose output psi^n is psi_n
-            l1 = rev1_node(a1, n1, i, x, y, l, set_step, psi_n1, P0n1, Bn1, psi_n, LT, LP0, u, v,
-                           gzx, gzy, cat, coef, ign, D, g1, cx1, cy1);
-            L1[i] = l1;
-            lp0 = LP0[i];
-            lt = LT[i];
+        if (q < kRTX * kRTY && x < nx && y < ny) {
+            const int i = y * nx + x;
+            const T gath = gather_lds(a, W, Dp, P0, x, y, ex, ey, x0, y0);
+            const T l = rev3_lds(a, i, x, y, L1i[i], W[ey][ex], gath, LP0, psi_n, ign, g3, cx3,
+                                 cy3);
+            T lo = l;
+            if (part1)
+                lo = rev1_node(a1, n1, i, x, y, l, set_step, psi_n1, P0n1, Bn1, psi_n, LT, LP0,
+                               u, v, gzx, gzy, cat, coef, ign, Do, g1, cx1, cy1);
+            L1o[i] = lo;
+            nz1 |= lo != T(0);
+            nzp |= LP0[i] != T(0);
+            nzt |= LT[i] != T(0);
         }
-        const int f1 = __syncthreads_or(l1 != T(0));
-        const int fp = __syncthreads_or(lp0 != T(0));
-        const int ft = __syncthreads_or(lt != T(0));
-        if (threadIdx.x == 0) {
-            fl.l1[b] = f1;
-            fl.lp0[b] = fp;
-            fl.lt[b] = ft;
-        }
-        shift_reduce(g3, cx3, cy3, a3.nign, acc, sh, b);
-        shift_reduce(g1, cx1, cy1, a1.nign, acc, sh, b);
-    };
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        block(b);
-        __syncthreads();
+        shift_reduce_rt(g3, cx3, cy3, a.nign, acc, sh, t);
+        shift_reduce_rt(g1, cx1, cy1, a1.nign, acc, sh, t);
     }
+    const int f1 = __syncthreads_or(nz1);
+    const int fp = __syncthreads_or(nzp);
+    const int ft = __syncthreads_or(nzt);
+    if (threadIdx.x == 0) {
+        f_l1o[t] = f1;
+        fl.lp0[t] = fp;
+        fl.lt[t] = ft;
+    }
+}
+
+// Per-tile flag of an array: whether any of the tile's values is nonzero.
+template <typename T>
+__global__ void __launch_bounds__(kAB) k_tile_any(const AdjArgs a, const T *p, int32_t *f) {
+    const int t = blockIdx.x;
+    const int x0 = (t % rtiles_x(a)) * kRTX, y0 = (t / rtiles_x(a)) * kRTY;
+    bool any = false;
+    for (int j = 0; j < 2; j++) {
+        const int q = threadIdx.x + j * kAB;
+        const int x = x0 + q % kRTX, y = y0 + q / kRTX;
+        if (x < a.nx && y < a.ny) any |= p[y * a.nx + x] != T(0);
+    }
+    const int r = __syncthreads_or(any);
+    if (threadIdx.x == 0) f[t] = r;
 }
 
 // Node times t^ on the extended mesh: t' where psi >= 0 and on the ghosts,
@@ -798,16 +865,11 @@ k_adj_frac(const AdjArgs a, const T *E, const T *TH, const T *lamF, const uint8_
 // dL/dt_i from dL/dt^ where t^ = t_i (psi < 0).
 template <typename T>
 __global__ void __launch_bounds__(kAB)
-k_lt_init(const AdjArgs a, const T *psi, const T *LTH, T *LT, int32_t *flag) {
+k_lt_init(const AdjArgs a, const T *psi, const T *LTH, T *LT) {
     const int i = blockIdx.x * kAB + threadIdx.x;
-    T lt = T(0);
-    if (i < a.nx * a.ny) {
-        const int x = i % a.nx, y = i / a.nx;
-        lt = psi[i] < T(0) ? LTH[ext_idx(a, x, y)] : T(0);
-        LT[i] = lt;
-    }
-    const int any = __syncthreads_or(lt != T(0));
-    if (threadIdx.x == 0) flag[blockIdx.x] = any;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    LT[i] = psi[i] < T(0) ? LTH[ext_idx(a, x, y)] : T(0);
 }
 
 template <typename T> __global__ void __launch_bounds__(kAB) k_set(T *p, T v, size_t cnt) {
@@ -874,6 +936,11 @@ struct fire_adj {
     double dt;
     int forward_done;
     int nblk, nblk_ext;
+    // The backward replays segment s - 1 on its own stream while segment s
+    // is reversed on the context's stream, into the other of two sets of
+    // replay buffers; events order the two.
+    hipStream_t rs;
+    hipEvent_t ev0, ev_rep[2], ev_rev[2];
 };
 
 namespace {
@@ -891,9 +958,9 @@ AdjLayout adj_layout(const fire_mesh *m, int ncat, int nsteps, int every) {
         o = align_up(o + bytes);
     };
     take(L.ckpt, (size_t)nseg * n * es);
-    take(L.stack, (size_t)(every + 1) * n * es);
-    take(L.rp0, (size_t)every * n * es);
-    take(L.rb, (size_t)every * n * es);
+    take(L.stack, 2 * (size_t)(every + 1) * n * es);   // two sets: segment parity
+    take(L.rp0, 2 * (size_t)every * n * es);
+    take(L.rb, 2 * (size_t)every * n * es);
     take(L.set_step, n * 4);
     take(L.flux, 2 * natm * es);
     take(L.e1, ne * es);
@@ -909,10 +976,11 @@ AdjLayout adj_layout(const fire_mesh *m, int ncat, int nsteps, int every) {
     take(L.gu, n * 8);
     take(L.gv, n * 8);
     take(L.gm, n * 8);
-    take(L.acc, nblk * kShift * 8);
+    const size_t ntile = (size_t)((m->nx + kRTX - 1) / kRTX) * ((m->ny + kRTY - 1) / kRTY);
+    take(L.acc, ntile * kShift * 8);
     take(L.part, nblk * (size_t)(ncat > kShift ? ncat : kShift) * 8);
     take(L.small, (size_t)(256 + kShift) * 8);
-    take(L.flags, 4 * nblk * sizeof(int32_t));   // AdjFlags: l1, lb, lp0, lt
+    take(L.flags, 4 * ntile * sizeof(int32_t));   // AdjFlags: l1[2], lp0, lt
     L.total = o;
     return L;
 }
@@ -927,20 +995,37 @@ template <typename T> struct Run {
 
     template <typename P> P *at(size_t off) { return reinterpret_cast<P *>(A->arena + off); }
     T *arr(size_t off) { return at<T>(off); }
-    T *stack(int k) { return arr(A->L.stack) + (size_t)k * n; }
-    T *rp0(int k) { return arr(A->L.rp0) + (size_t)k * n; }   // psi' of step k
-    T *rb(int k) { return arr(A->L.rb) + (size_t)k * n; }     // psi* of step k
+    // replay buffers of segment parity p: psi before step k of the segment,
+    // psi' and psi* of step k
+    T *stack(int p, int k) {
+        return arr(A->L.stack) + ((size_t)p * (A->every + 1) + k) * n;
+    }
+    T *rp0(int p, int k) { return arr(A->L.rp0) + ((size_t)p * A->every + k) * n; }
+    T *rb(int p, int k) { return arr(A->L.rb) + ((size_t)p * A->every + k) * n; }
     const T *coef() { return reinterpret_cast<const T *>(c->arena + c->off_coef); }
     const fire_ignition *ign() {
         return reinterpret_cast<const fire_ignition *>(c->arena + c->off_ign);
     }
     const T *cur_psi() { return reinterpret_cast<const T *>(c->arena + c->off_psi[c->cur]); }
     const T *tign_final() { return reinterpret_cast<const T *>(c->arena + c->off_tign); }
+    // reverse-pass tiles, the per-tile flags, and the two buffers of
+    // dL/dpsi^{n+1} and of the stage-2 partials (cur: the current one)
+    int ntile() const {
+        return ((c->mesh.nx + kRTX - 1) / kRTX) * ((c->mesh.ny + kRTY - 1) / kRTY);
+    }
     AdjFlags flags() {
         int32_t *f = at<int32_t>(A->L.flags);
-        const size_t nb = (n + kAB - 1) / kAB;
-        return AdjFlags{f, f + nb, f + 2 * nb, f + 3 * nb};
+        const int nt = ntile();
+        AdjFlags r;
+        r.l1[0] = f;
+        r.l1[1] = f + nt;
+        r.lp0 = f + 2 * nt;
+        r.lt = f + 3 * nt;
+        return r;
     }
+    int cur = 0;
+    T *l1buf(int k) { return arr(k ? A->L.lb : A->L.l1); }
+    T *dbuf(int k) { return arr(k ? A->L.d1 : A->L.d); }
     // whether any ignition is active at time t (the test of ign_setup)
     int ign_active_at(double t) const {
         for (int g = 0; g < c->nign; g++) {
@@ -991,74 +1076,81 @@ template <typename T> struct Run {
         hipLaunchKernelGGL(k_adj_corners<T>, dim3(1), dim3(64), 0, s, a, arr(A->L.e1),
                            arr(A->L.le));
         const AdjFlags fl = flags();
+        const int nt = ntile();
+        cur = 0;
         hipLaunchKernelGGL(k_adj_ghostT<T>, dim3(gn), dim3(kAB), 0, s, a, psiN, arr(A->L.le),
                            (const T *)nullptr, (const T *)nullptr, T(0), (const T *)nullptr,
-                           arr(A->L.l1), fl.l1);
+                           l1buf(0));
         hipLaunchKernelGGL(k_lt_init<T>, dim3(gn), dim3(kAB), 0, s, a, psiN, arr(A->L.e2),
-                           arr(A->L.lt), fl.lt);
-        // LB and LP0 hold whatever the arena held: flagged, so a block that
-        // skips its work clears them
-        hipLaunchKernelGGL(k_set<int32_t>, dim3(gn), dim3(kAB), 0, s, fl.lb, 1, (size_t)gn);
-        hipLaunchKernelGGL(k_set<int32_t>, dim3(gn), dim3(kAB), 0, s, fl.lp0, 1, (size_t)gn);
+                           arr(A->L.lt));
+        hipLaunchKernelGGL(k_tile_any<T>, dim3(nt), dim3(kAB), 0, s, a, l1buf(0), fl.l1[0]);
+        hipLaunchKernelGGL(k_tile_any<T>, dim3(nt), dim3(kAB), 0, s, a, arr(A->L.lt), fl.lt);
+        // the second buffer and LP0 hold whatever the arena held: flagged, so
+        // a tile that skips its work clears them
+        hipLaunchKernelGGL(k_set<int32_t>, dim3(nt), dim3(kAB), 0, s, fl.l1[1], 1, (size_t)nt);
+        hipLaunchKernelGGL(k_set<int32_t>, dim3(nt), dim3(kAB), 0, s, fl.lp0, 1, (size_t)nt);
         return hipGetLastError();
     }
 
+    // Replays segment seg on the replay stream into the buffers of its
+    // parity.
     hipError_t replay(int seg) {
+        const int p = seg & 1;
         const int s0 = seg * A->every;
         const int s1 = s0 + A->every < A->nsteps ? s0 + A->every : A->nsteps;
-        hipError_t h = hipMemcpyAsync(stack(0), arr(A->L.ckpt) + (size_t)seg * n, n * sizeof(T),
-                                      hipMemcpyDeviceToDevice, s);
+        hipError_t h = hipMemcpyAsync(stack(p, 0), arr(A->L.ckpt) + (size_t)seg * n,
+                                      n * sizeof(T), hipMemcpyDeviceToDevice, A->rs);
         if (h != hipSuccess) return h;
         // psi does not depend on ignition times or fuel fraction: the replay
         // recomputes psi, psi' and psi* only
         for (int k = s0; k < s1; k++) {
-            h = step_raw(c, stack(k - s0), stack(k - s0 + 1), nullptr, nullptr, A->u, A->v,
-                         A->tstep[k], A->dt, nullptr, nullptr, nullptr, rp0(k - s0), rb(k - s0));
+            h = step_raw(c, stack(p, k - s0), stack(p, k - s0 + 1), nullptr, nullptr, A->u, A->v,
+                         A->tstep[k], A->dt, nullptr, nullptr, nullptr, rp0(p, k - s0),
+                         rb(p, k - s0), A->rs);
             if (h != hipSuccess) return h;
         }
         return hipGetLastError();
     }
 
     // Reverse the steps of one replayed segment [s0, s1): part 1 of the last
-    // step, then per step part 2 and part 3 fused with part 1 of the step
-    // before it (part 3 alone for the first step of the segment).
+    // step, then one tiled pass per step (parts 2 and 3, with part 1 of the
+    // step before it except for the first step of the segment).
     hipError_t reverse_segment(int s0, int s1) {
+        const int p = (s0 / A->every) & 1;
         const T *u = (const T *)A->u, *v = (const T *)A->v;
         const T *gx = (const T *)c->dzdx, *gy = (const T *)c->dzdy;
-        T *L1 = arr(A->L.l1), *LT = arr(A->L.lt), *LP0 = arr(A->L.lp0), *LB = arr(A->L.lb);
-        T *D = arr(A->L.d), *D1 = arr(A->L.d1);
+        T *LT = arr(A->L.lt), *LP0 = arr(A->L.lp0);
         double *gu = at<double>(A->L.gu), *gv = at<double>(A->L.gv), *gm = at<double>(A->L.gm);
         double *acc = at<double>(A->L.acc);
         const int32_t *set_step = at<int32_t>(A->L.set_step);
         const AdjFlags fl = flags();
-        // one work-group per node block: walking several blocks per
-        // work-group measured slower (each skip still waits for its flags)
-        const int rg = gn;
+        const int nt = ntile();
         AdjArgs an = a;
         an.t = A->tstep[s1 - 1];
         an.ign_active = ign_active_at(an.t);
         int k = s1 - 1 - s0;
-        hipLaunchKernelGGL(k_rev_stage2<T>, dim3(rg), dim3(kAB), 0, s, an, s1 - 1, set_step,
-                           stack(k), rp0(k), rb(k), stack(k + 1), L1, LT, LP0, u, v, gx, gy,
-                           c->cat, coef(), ign(), D, acc, fl);
+        hipLaunchKernelGGL(k_rev_part1<T>, dim3(nt), dim3(kAB), 0, s, an, s1 - 1, set_step,
+                           stack(p, k), rp0(p, k), rb(p, k), stack(p, k + 1), l1buf(cur),
+                           fl.l1[cur], LT, LP0,
+                           u, v, gx, gy, c->cat, coef(), ign(), dbuf(cur), acc, fl);
         for (int n_ = s1 - 1; n_ >= s0; n_--) {
             k = n_ - s0;
             an.t = A->tstep[n_];
             an.ign_active = ign_active_at(an.t);
-            hipLaunchKernelGGL(k_rev_stage1<T>, dim3(rg), dim3(kAB), 0, s, an, D, rb(k), L1, LB,
-                               rp0(k), u, v, gx, gy, c->cat, coef(), D1, gu, gv, gm, fl);
-            if (n_ > s0) {
-                AdjArgs ap = a;
-                ap.t = A->tstep[n_ - 1];
-                ap.ign_active = ign_active_at(ap.t);
-                hipLaunchKernelGGL(k_rev_psi_stage2<T>, dim3(rg), dim3(kAB), 0, s, an, ap,
-                                   n_ - 1, D1, rp0(k), LP0, LB, stack(k), set_step, stack(k - 1),
-                                   rp0(k - 1), rb(k - 1), L1, LT, u, v, gx, gy, c->cat, coef(),
-                                   ign(), D, acc, fl);
-            } else {
-                hipLaunchKernelGGL(k_rev_psi<T>, dim3(rg), dim3(kAB), 0, s, an, D1, rp0(k), LP0,
-                                   LB, stack(k), ign(), L1, acc, fl);
-            }
+            const int part1 = n_ > s0 ? 1 : 0;
+            AdjArgs ap = a;
+            ap.t = part1 ? A->tstep[n_ - 1] : an.t;
+            ap.ign_active = ign_active_at(ap.t);
+            hipLaunchKernelGGL(k_rev_tile<T>, dim3(nt), dim3(kRT), 0, s, an, ap, part1, n_ - 1,
+                               (const T *)dbuf(cur), (const T *)l1buf(cur),
+                               (const int32_t *)fl.l1[cur], (const T *)rb(p, k),
+                               (const T *)rp0(p, k), (const T *)stack(p, k), LP0, l1buf(1 - cur),
+                               fl.l1[1 - cur], dbuf(1 - cur), set_step,
+                               part1 ? (const T *)stack(p, k - 1) : nullptr,
+                               part1 ? (const T *)rp0(p, k - 1) : nullptr,
+                               part1 ? (const T *)rb(p, k - 1) : nullptr, LT, u, v, gx, gy, c->cat,
+                               coef(), ign(), gu, gv, gm, acc, fl);
+            cur = 1 - cur;
         }
         return hipGetLastError();
     }
@@ -1067,13 +1159,27 @@ template <typename T> struct Run {
         hipError_t h = zero_d(A->L.gu, n);
         if (h == hipSuccess) h = zero_d(A->L.gv, n);
         if (h == hipSuccess) h = zero_d(A->L.gm, n);
-        if (h == hipSuccess) h = zero_d(A->L.acc, (size_t)gn * kShift);
+        if (h == hipSuccess) h = zero_d(A->L.acc, (size_t)ntile() * kShift);
         if (h == hipSuccess) h = loss_init(dF);
+        // the replay stream starts after everything enqueued so far (the
+        // forward's checkpoints); segment seg - 1 is replayed while seg is
+        // reversed, once the reversal two segments back has freed its buffers
+        if (h == hipSuccess) h = hipEventRecord(A->ev0, s);
+        if (h == hipSuccess) h = hipStreamWaitEvent(A->rs, A->ev0, 0);
+        if (h == hipSuccess) h = replay(A->nseg - 1);
+        if (h == hipSuccess) h = hipEventRecord(A->ev_rep[(A->nseg - 1) & 1], A->rs);
         for (int seg = A->nseg - 1; seg >= 0 && h == hipSuccess; seg--) {
             const int s0 = seg * A->every;
             const int s1 = s0 + A->every < A->nsteps ? s0 + A->every : A->nsteps;
-            h = replay(seg);
+            if (seg >= 1) {
+                const int q = (seg - 1) & 1;
+                if (seg + 1 < A->nseg) h = hipStreamWaitEvent(A->rs, A->ev_rev[q], 0);
+                if (h == hipSuccess) h = replay(seg - 1);
+                if (h == hipSuccess) h = hipEventRecord(A->ev_rep[q], A->rs);
+            }
+            if (h == hipSuccess) h = hipStreamWaitEvent(s, A->ev_rep[seg & 1], 0);
             if (h == hipSuccess) h = reverse_segment(s0, s1);
+            if (h == hipSuccess) h = hipEventRecord(A->ev_rev[seg & 1], s);
         }
         if (h != hipSuccess) return FIRE_ERR_HIP;
         // outputs
@@ -1085,8 +1191,8 @@ template <typename T> struct Run {
         hipLaunchKernelGGL(k_cat_partial, dim3(gn), dim3(kAB), 0, s, at<double>(A->L.gm), c->cat,
                            (int)n, c->ncat, part);
         hipLaunchKernelGGL(k_col_sum, dim3(c->ncat), dim3(kAB), 0, s, part, gn, c->ncat, small);
-        hipLaunchKernelGGL(k_col_sum, dim3(kShift), dim3(kAB), 0, s, at<double>(A->L.acc), gn,
-                           kShift, small + 256);
+        hipLaunchKernelGGL(k_col_sum, dim3(kShift), dim3(kAB), 0, s, at<double>(A->L.acc),
+                           ntile(), kShift, small + 256);
         h = hipGetLastError();
         if (h == hipSuccess)
             h = hipMemcpyAsync(grad_mult, small, sizeof(double) * c->ncat, hipMemcpyDeviceToHost,
@@ -1134,6 +1240,17 @@ int fire_adj_init(fire_adj **out, fire_ctx *c, int32_t nsteps, int32_t every, vo
     A->u = A->v = nullptr;
     A->dt = 0.0;
     A->forward_done = 0;
+    A->rs = nullptr;
+    A->ev0 = A->ev_rep[0] = A->ev_rep[1] = A->ev_rev[0] = A->ev_rev[1] = nullptr;
+    bool ok = hipStreamCreateWithFlags(&A->rs, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&A->ev0, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 2 && ok; k++)
+        ok = hipEventCreateWithFlags(&A->ev_rep[k], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&A->ev_rev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        fire_adj_destroy(A);
+        return FIRE_ERR_HIP;
+    }
     *out = A;
     return FIRE_OK;
 }
@@ -1192,6 +1309,13 @@ int fire_adj_backward(fire_adj *A, const void *dF, void *grad_u, void *grad_v, d
     return r.backward((const float *)dF, (float *)grad_u, (float *)grad_v, grad_mult, grad_shift);
 }
 
-void fire_adj_destroy(fire_adj *A) { delete A; }
+void fire_adj_destroy(fire_adj *A) {
+    if (!A) return;
+    if (A->rs) (void)hipStreamSynchronize(A->rs);
+    for (hipEvent_t e : {A->ev0, A->ev_rep[0], A->ev_rep[1], A->ev_rev[0], A->ev_rev[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (A->rs) (void)hipStreamDestroy(A->rs);
+    delete A;
+}
 
 }  // extern "C"

@@ -135,7 +135,8 @@ namespace fire {
 // arena for fire_step, replay buffers for the adjoint).
 hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
                     const void *u, const void *v, double t, double dt, void *flux_sens,
-                    void *flux_lat, int *status, void *rec_p0, void *rec_b) {
+                    void *flux_lat, int *status, void *rec_p0, void *rec_b,
+                    hipStream_t stream) {
     const fire_mesh &m = c->mesh;
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -193,7 +194,7 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     b.mark = rec_p0 ? nullptr : c->mark;
     a.mark_step = c->mark_step;
 
-    return launch_step(m.dtype, a, b, c->stream);
+    return launch_step(m.dtype, a, b, stream ? stream : c->stream);
 }
 
 }  // namespace fire

@@ -174,6 +174,7 @@ bool tile_ok(const fire_mesh *m, int tile_x, int tile_y);
 void ignition_window(const fire_ignition *ign, int n, double *lo, double *hi);
 hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, void *frac,
                     const void *u, const void *v, double t, double dt, void *flux_sens,
-                    void *flux_lat, int *status, void *rec_p0 = nullptr, void *rec_b = nullptr);
+                    void *flux_lat, int *status, void *rec_p0 = nullptr, void *rec_b = nullptr,
+                    hipStream_t stream = nullptr);   // null: the context's stream
 
 }  // namespace fire

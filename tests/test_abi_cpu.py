@@ -119,9 +119,10 @@ def test_adjoint_sizes_and_errors_without_gpu(lib):
     m = F.fire_mesh(100, 80, 6.0, 6.0, 10, 10, F.FIRE_F32, 0)
     n = 100 * 80
     nb = lib.fire_adj_bytes(C.byref(m), 13, 500, 50)
-    # 10 checkpoints + 51 stack levels of psi, plus the working arrays
-    assert nb >= (10 + 51) * 4 * n
-    assert nb <= (10 + 51 + 40) * 8 * n
+    # 10 checkpoints, two sets of replay buffers (51 levels of psi, 50 of
+    # psi' and of psi* each), plus the working arrays
+    assert nb >= (10 + 2 * 151) * 4 * n
+    assert nb <= (10 + 2 * 151 + 40) * 4 * n
     assert lib.fire_adj_bytes(C.byref(m), 13, 0, 50) == 0
     assert lib.fire_adj_bytes(C.byref(m), 13, 500, 0) == 0
     assert lib.fire_adj_bytes(C.byref(m), 0, 500, 50) == 0

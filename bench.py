@@ -43,6 +43,10 @@ def workload(name):
         p = synth.patchy_fire(n=8192, steps=1000, nwind=4, wind_period=10,
                               field_dtype=np.float32)
         return p, "f32"
+    if name == "patchy8192_burning":
+        p = synth.patchy_fire(n=8192, steps=1000, nwind=4, wind_period=10,
+                              field_dtype=np.float32)
+        return p, "f32"
     if name == "patchy2048":
         p = synth.patchy_fire(n=2048, steps=2000, field_dtype=np.float32)
         return p, "f32"
@@ -168,7 +172,8 @@ def main():
                     help="timed steps (default: the workload's own step count, at most 1000)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="patchy8192",
-                    choices=("patchy8192", "patchy2048", "uniform128", "ensemble256",
+                    choices=("patchy8192", "patchy8192_burning", "patchy2048", "uniform128",
+                             "ensemble256",
                              "adjoint1024", "wind8192"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -223,6 +228,11 @@ def main():
     tdt = torch.float32 if dtype == "f32" else torch.float64
     stream = torch.cuda.current_stream()
     fire = F.Fire.from_problem(prob, dtype=tdt)
+    if args.workload == "patchy8192_burning":
+        from paper_1102_1343_amd import synth
+        psi, tign, frac, t0 = synth.burning_state(prob)
+        fire.set_state(psi, tign, frac, t0)
+        log(f"state set at t = {t0} s with {float((psi < 0).mean()):.3f} of the mesh burning")
     if args.tile:
         fire.set_tile(*[int(x) for x in args.tile.split(",")])
     winds = [(torch.from_numpy(np.ascontiguousarray(u)).to("cuda", tdt),

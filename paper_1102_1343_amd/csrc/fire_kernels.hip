@@ -100,6 +100,15 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
         }
     // edge midpoints and corners shared by neighbouring sub-cells
     const T pc = p[1][1], qc = q[1][1];
+    T pmax = p[0][0];
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) pmax = vmax(pmax, p[b][a]);
+    // every node burning: every sub-cell corner value is a mean of negative
+    // values, so beta = 1 exactly in all four sub-cells (Eq. 18) and t^ is
+    // t_i at every corner; the sums keep the general path's order
+    const bool all_burning = pmax < T(0);
     T pe[2][2], qe[2][2];   // [0][s]: x edges (s = left/right), [1][s]: y edges
 #pragma unroll
     for (int s = 0; s < 2; s++) {
@@ -117,6 +126,13 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
                              T(0.25) * (pc + p[1][2 * sa] + p[2 * sb][1] + p[2 * sb][2 * sa])};
             const T qk[4] = {qc, qe[0][sa], qe[1][sb],
                              T(0.25) * (qc + q[1][2 * sa] + q[2 * sb][1] + q[2 * sb][2 * sa])};
+            if (all_burning) {
+                T tau = T(0);
+#pragma unroll
+                for (int k = 0; k < 4; k++) tau += tp - qk[k];
+                burned += M<T>::one_m_exp_neg(T(0.25) * tau * rTf);
+                continue;
+            }
             T sum = T(0), asum = T(0), tau = T(0);
 #pragma unroll
             for (int k = 0; k < 4; k++) {

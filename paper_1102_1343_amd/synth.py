@@ -287,6 +287,31 @@ def patchy_fire(n=2048, dx=6.0, steps=2000, dt=0.25, nwind=1, wind_period=0,
                    name=f"patchy{n}")
 
 
+def burning_state(prob: Problem, frac_burning=0.4, nfires=64, t0=60.0, spread=2.0,
+                  seed=SEED, dtype=np.float32):
+    """A mid-run state with a large burning area, to time the step where the
+    fuel-fraction quadrature runs on much of the mesh: ``nfires`` discs at
+    seeded centres whose union covers about ``frac_burning`` of the domain
+    (radius r from Poisson coverage); psi = distance to the nearest centre
+    less r within 1.5 r of a centre and 0.5 r beyond, ignition times
+    t0 - (r - distance)/``spread`` inside the discs (+inf outside), F = 1
+    everywhere, model time t0 (past the patchy ignitions' windows).  Returns
+    (psi, tign, frac, t0) as [ny][nx] arrays."""
+    rng = np.random.default_rng([seed, 99])
+    W, H = prob.nx * prob.dx, prob.ny * prob.dy
+    r = math.sqrt(-math.log(1.0 - frac_burning) * W * H / (nfires * math.pi))
+    psi = np.full((prob.ny, prob.nx), 0.5 * r)
+    for a, b in zip(rng.uniform(0.0, W, nfires), rng.uniform(0.0, H, nfires)):
+        i0, i1 = max(0, int((a - 1.5 * r) / prob.dx)), min(prob.nx, int((a + 1.5 * r) / prob.dx) + 1)
+        j0, j1 = max(0, int((b - 1.5 * r) / prob.dy)), min(prob.ny, int((b + 1.5 * r) / prob.dy) + 1)
+        x = (np.arange(i0, i1) + 0.5) * prob.dx - a
+        y = ((np.arange(j0, j1) + 0.5) * prob.dy - b)[:, None]
+        psi[j0:j1, i0:i1] = np.minimum(psi[j0:j1, i0:i1], np.hypot(x[None, :], y) - r)
+    tign = np.where(psi < 0, t0 + psi / spread, np.inf)
+    frac = np.ones_like(psi)
+    return psi.astype(dtype), tign.astype(dtype), frac.astype(dtype), float(t0)
+
+
 def window(prob: Problem, i0: int, j0: int, w: int, h: int) -> Problem:
     """The sub-mesh [j0:j0+h, i0:i0+w] of ``prob`` as a problem of its own:
     arrays sliced, ignition coordinates shifted to the window origin.  With

@@ -25,11 +25,16 @@ def _log(msg):
     print(msg, flush=True)
 
 
-def run_fp64(prob, steps, tile=None, **kw):
+def run_fp64(prob, steps, tile=None, state=None, **kw):
     _log(f"fp64 parity {prob.name} {prob.nx}x{prob.ny} steps={steps} tile={tile}")
     g = gpu_fire(prob, torch.float64, tile=tile, **kw)
     o = oracle.OracleFire(prob, **{k: v for k, v in kw.items()
                                    if k in ("viscosity", "viscosity_mode", "ros_cap", "guard_width")})
+    if state is not None:   # (psi, t_i, F, t) on both sides
+        psi, tign, frac, t0 = state
+        g.set_state(psi, tign, frac, t0)
+        o.psi, o.tign, o.frac = (np.array(a, dtype=np.float64) for a in (psi, tign, frac))
+        o.t = float(t0)
     W = wind_tensors(prob, torch.float64)
     cmp = Compare64(prob)
     fs, fl = g.new_flux()
@@ -91,6 +96,16 @@ def test_patchy_fp64():
     prob = synth.patchy_fire(n=240, steps=240)
     g, o = run_fp64(prob, prob.steps)
     assert np.isfinite(o.tign).sum() > 100
+
+
+def test_burning_state_fp64():
+    """A state with 40 % of the mesh burning (ignition times up to ~10 min in
+    the past, F = 1): the fuel-fraction quadrature and the flux path run on
+    much of the mesh every step."""
+    prob = synth.patchy_fire(n=300, steps=40)
+    state = synth.burning_state(prob, frac_burning=0.4, nfires=6, dtype=np.float64)
+    g, o = run_fp64(prob, prob.steps, state=state)
+    assert (o.frac < 1).mean() > 0.3
 
 
 def test_patchy_fp64_other_tiles_and_wind_changes():

@@ -130,7 +130,10 @@ typedef struct {
 
 /* Bytes of caller-owned device memory the state arena needs for this mesh
  * and number of fuel categories (psi double buffer, t_i, F, coefficient
- * table, status word).  Returns 0 for an invalid mesh. */
+ * table, status word, and the step's ignition set-up: a 4-byte word and 8
+ * bounds per tile of the default tile shape and 16 offsets per mesh row,
+ * ntiles (4 + 8 e) + 16 (ny + 48) e bytes for element size e).  Returns 0
+ * for an invalid mesh. */
 size_t fire_state_bytes(const fire_mesh *mesh, int32_t ncat);
 
 /*

@@ -95,8 +95,17 @@ bool tile_ok(const fire_mesh *m, int tile_x, int tile_y) {
 namespace {
 
 struct Layout {
-    size_t coef, fuel, ign, geo, status, psi0, psi1, tign, frac, total;
+    size_t coef, fuel, ign, geo, iset, status, psi0, psi1, tign, frac, total;
+    int tile_cap;
 };
+
+// tiles at the mesh's default tile shape: the capacity of the per-tile
+// ignition set-up
+int default_tiles(const fire_mesh *m) {
+    int tx, ty;
+    default_tile(m, &tx, &ty);
+    return ((m->nx + tx - 1) / tx) * ((m->ny + ty - 1) / ty);
+}
 
 Layout layout(const fire_mesh *m, int ncat) {
     const size_t n = (size_t)m->nx * m->ny, e = esize(m);
@@ -110,6 +119,9 @@ Layout layout(const fire_mesh *m, int ncat) {
     o = align_up(o + FIRE_MAX_IGNITIONS * sizeof(fire_ignition));
     L.geo = o;
     o = align_up(o + kIgnTableBytes);
+    L.tile_cap = default_tiles(m);
+    L.iset = o;
+    o = align_up(o + ign_set_layout(L.tile_cap, m->ny, e).total);
     L.status = o;
     o = align_up(o + 64);
     L.psi0 = o;
@@ -193,6 +205,9 @@ hipError_t step_raw(fire_ctx *c, const void *psi_in, void *psi_out, void *tign, 
     b.rec_b = rec_b;
     b.mark = rec_p0 ? nullptr : c->mark;
     a.mark_step = c->mark_step;
+    a.tile_cap = c->tile_cap;
+    a.ign_rows = m.ny + kFHMax;
+    b.ign_set = state_ptr(c, c->off_iset);
 
     return launch_step(m.dtype, a, b, stream ? stream : c->stream);
 }
@@ -250,6 +265,8 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
     c->off_fuel = L.fuel;
     c->off_ign = L.ign;
     c->off_geo = L.geo;
+    c->off_iset = L.iset;
+    c->tile_cap = L.tile_cap;
     c->off_status = L.status;
     c->off_psi[0] = L.psi0;
     c->off_psi[1] = L.psi1;

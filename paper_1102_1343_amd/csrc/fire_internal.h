@@ -39,6 +39,7 @@ struct StepArgs {
     int32_t tiles_x, ntiles, per_xcd;   // ntiles: total tiles of the launch
     int32_t sr_x, sr_y, nax, nay;
     int32_t ncat, guard, visc_mode, nign, mark_step;   // mark_step: see StepBuffers::mark
+    int32_t tile_cap, ign_rows;   // plain step: see IgnSetLayout
     double dx, dy;
     double rdx, rdy;     // 1/dx, 1/dy
     double t, dt;        // t unused by the ensemble kernel (device time)
@@ -63,6 +64,31 @@ template <typename T> struct IgnTable {
 };
 // bytes reserved per domain for its table (room for either precision)
 constexpr size_t kIgnTableBytes = (sizeof(IgnTable<double>) + 255) / 256 * 256;
+
+// Per-tile ignition set-up of a single domain's step, formed with the
+// geometry ahead of the step kernel, so the step reads it with scalar loads:
+//  * use[tile] (tile < tile_cap), 2 bits per ignition g at bit 2g: 0 the
+//    ignition cannot change the tile's frame, 1 it can lower psi but lights
+//    no node there (psi_g > 0 on the whole frame), 2 it may light nodes;
+//    use[tile_cap] is the word for tiles past the capacity (2 for every
+//    active ignition);
+//  * lb[tile][g], a lower bound of psi_g over the tile's frame;
+//  * rows[g][gy + kHalo] and rows[FIRE_MAX_IGNITIONS + g][gy + kHalo], the
+//    node-row offsets py and by of global row gy, for gy in
+//    [-kHalo, ny + kFHMax - kHalo) (every frame row of every tile).
+// tile_cap is the tile count at the mesh's default tile shape.
+struct IgnSetLayout {
+    size_t use, lb, rows, total;
+};
+inline IgnSetLayout ign_set_layout(int tile_cap, int ny, size_t esz) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    IgnSetLayout L;
+    L.use = 0;
+    L.lb = up((size_t)(tile_cap + 1) * sizeof(uint32_t));
+    L.rows = L.lb + up((size_t)tile_cap * FIRE_MAX_IGNITIONS * esz);
+    L.total = L.rows + up((size_t)2 * FIRE_MAX_IGNITIONS * (ny + kFHMax) * esz);
+    return L;
+}
 
 // One member of an ensemble (device table row).
 struct EnsDomain {
@@ -107,6 +133,8 @@ struct StepBuffers {
                                         // and psi* only (one domain)
     int32_t *mark;                      // non-null (plain step): mark[i] = mark_step at
                                         // each node whose ignition time the step sets
+    void *ign_set;                      // plain step: the per-tile ignition set-up
+                                        // (IgnSetLayout), null for an ensemble
 };
 
 }  // namespace fire
@@ -123,7 +151,9 @@ struct fire_ctx {
     const uint8_t *cat;
     const void *dzdx, *dzdy;
     char *arena;
-    size_t off_coef, off_fuel, off_ign, off_geo, off_status, off_psi[2], off_tign, off_frac;
+    size_t off_coef, off_fuel, off_ign, off_geo, off_iset, off_status, off_psi[2], off_tign,
+        off_frac;
+    int tile_cap;          // tiles at the default tile shape (IgnSetLayout)
     int cur;               // index of the current psi buffer
     double t;              // model time of the current state
     hipStream_t stream;

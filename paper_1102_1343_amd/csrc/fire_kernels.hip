@@ -83,6 +83,63 @@ __device__ __forceinline__ void ghost_node(T (*P)[kFW], int fy, int fx, int gx, 
     }
 }
 
+// Lane permutations within each row of 16 lanes (DPP): swap neighbours,
+// swap pairs, mirror each half row, mirror the row.  A lane whose source is
+// unavailable keeps its own value.
+template <int CTRL> __device__ __forceinline__ float dpp(float x) {
+    const int i = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
+}
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Largest value over the wave's 64 lanes (NaN ignored, as by vmax), the same
+// in every lane: the maximum of each 16-lane row by four lane permutations,
+// then of the four rows.  The wave must have every lane active.
+template <typename T> __device__ __forceinline__ T wave_reduce_max(T m) {
+    m = vmax(m, dpp<0xB1>(m));    // quad_perm [1, 0, 3, 2]
+    m = vmax(m, dpp<0x4E>(m));    // quad_perm [2, 3, 0, 1]
+    m = vmax(m, dpp<0x141>(m));   // row_half_mirror
+    m = vmax(m, dpp<0x140>(m));   // row_mirror
+    return vmax(vmax(lane_value(m, 0), lane_value(m, 16)),
+                vmax(lane_value(m, 32), lane_value(m, 48)));
+}
+
+// Bounds of psi_g (Eq. 21) over the nodes of a frame of kFW columns and fh
+// rows whose first node is global (fx0, fy0): the distance from the frame's
+// centre to the segment -/+ the frame's half diagonal, less the radius,
+// widened by a margin (1 m + 1e-4 of the distances) far above the rounding of
+// psi_g and of the bounds themselves.  Node (i, j) sits at ((i + 1/2) dx,
+// (j + 1/2) dy), so the centre is (fx0 + kFW/2, fy0 + fh/2) cells.
+template <typename T>
+__device__ __forceinline__ void ign_frame_bounds(const IgnGeo<T> &gs, int fx0, int fy0, int fh,
+                                                 double dx, double dy, T &lb, T &ub) {
+    const T cx = T((fx0 + 0.5 * kFW) * dx - gs.ax);
+    const T cy = T((fy0 + 0.5 * fh) * dy - gs.ay);
+    const T hx = T(0.5 * (kFW - 1)) * T(dx), hy = T(0.5 * (fh - 1)) * T(dy);
+    const T hd = M<T>::sqrt(hx * hx + hy * hy);
+    const T sp = med3(cx * gs.exL + cy * gs.eyL, T(0), T(1));
+    const T qx = cx - sp * gs.ex, qy = cy - sp * gs.ey;
+    const T d = M<T>::sqrt(qx * qx + qy * qy);
+    const T mg = T(1) + T(1e-4) * (d + M<T>::sqrt(gs.ex * gs.ex + gs.ey * gs.ey));
+    lb = d - hd - gs.rad - mg;
+    ub = d + hd - gs.rad + mg;
+}
+
 // Fuel fraction of one cell at t' (Eqs. 15-19) from the 3x3 node values of
 // psi^{n+1} (A) and of the node ignition times t^ (Q, already t' where
 // psi >= 0).  Four sub-cells with corners at the centre, two edge midpoints
@@ -149,7 +206,9 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 // The fused step.  KR = frame rows per thread (frame height <= 4 KR).
 // LDS frames: A holds psi^n, then psi^{n+1}, then the latent flux; B holds
 // psi*, then the sensible flux; C holds the node ignition times t^.
-template <typename T, int KR, bool SMALL, bool REC>
+// PRE: the per-tile ignition set-up comes from iuse / ilb / irow (a single
+// domain's step); otherwise it is formed here from the geometry table.
+template <typename T, int KR, bool SMALL, bool REC, bool PRE>
 __device__ __forceinline__ void
 step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const uint32_t cbase,
           const double tnow,
@@ -157,7 +216,8 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
           const T *__restrict__ uw, const T *__restrict__ vw, const T *__restrict__ dzdx,
           const T *__restrict__ dzdy, const uint8_t *__restrict__ cat, const T *__restrict__ coef,
           T *__restrict__ fsens, T *__restrict__ flat, int *status, T *rec_p0, T *rec_b,
-          int32_t *mark) {
+          int32_t *mark, const uint32_t *__restrict__ iuse, const T *__restrict__ ilb,
+          const T *__restrict__ irow) {
     constexpr int FHM = kNR * KR;
     __shared__ T A[FHM][kFW];
     __shared__ T B[FHM][kFW];
@@ -231,7 +291,45 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
         p0[k] = in ? at<SMALL>(psi_in, idx0 + roff(k)) : T(0);
         tig[k] = INF;
     }
-    if (a.nign > 0) {
+    if (PRE && a.nign > 0) {
+        // the tile's set-up, formed ahead of the step (IgnSetLayout): how
+        // each ignition enters the tile and a lower bound of its psi_g there;
+        // the row offsets py, by of the wave's frame rows.  No barrier: an
+        // ignition that can only lower psi is skipped by a wave whose
+        // largest psi^n (NaN nodes, which no ignition changes, ignored) is no
+        // larger than that bound.
+        T m = -INF;
+#pragma unroll
+        for (int k = 0; k < KR; k++) m = vmax(m, p0[k]);
+        m = wave_reduce_max(m);
+        const uint32_t word = iuse[tile < a.tile_cap ? tile : a.tile_cap];
+        // a wave's 64 lanes share one frame row
+        const int tyu = __builtin_amdgcn_readfirstlane(ty);
+        T pold[KR];
+#pragma unroll
+        for (int k = 0; k < KR; k++) pold[k] = p0[k];
+        for (int g = 0; g < a.nign; g++) {
+            const int use = (word >> (2 * g)) & 3;
+            if (!use) continue;
+            // (use 1 occurs only for tiles below the capacity)
+            if (use == 1 && ilb[(size_t)tile * FIRE_MAX_IGNITIONS + g] >= m) continue;
+            const IgnGeo<T> geo = itab->g[g];
+            const T px = ign_px(geo, gx, a.dx);
+            // global row gy = y0 - kHalo + fy is table row y0 + fy
+            const T *rpy = irow + (size_t)g * a.ign_rows + y0 + tyu;
+            const T *rby = irow + (size_t)(FIRE_MAX_IGNITIONS + g) * a.ign_rows + y0 + tyu;
+            if (use == 2) {
+#pragma unroll
+                for (int k = 0; k < KR; k++) ign_apply(geo, px, rpy[kNR * k], rby[kNR * k], p0[k], tig[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < KR; k++) ign_lower(geo, px, rpy[kNR * k], rby[kNR * k], p0[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KR; k++)
+            if (!(pold[k] > T(0) && p0[k] <= T(0))) tig[k] = INF;
+    } else if (a.nign > 0) {
         // the step's geometry of each ignition (lane g of the first wave
         // takes ignition g) and its per-row offsets py, by for the frame
         // rows, shared through LDS
@@ -247,23 +345,9 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
             const bool on = itab->on[tid] != 0;
             geo_on[tid] = on ? 1 : 0;
             geo_s[tid] = gs;
-            if (on) {
-                // bounds of psi_g over the frame nodes: distance from the
-                // frame's centre to the segment, -/+ its half diagonal, less
-                // the radius, widened by a margin (1 m + 1e-4 of the
-                // distances) far above the rounding of psi_g and of the
-                // bounds themselves
-                const T cx = T((x0 - kHalo + 0.5 * kFW - 0.5) * a.dx - gs.ax);
-                const T cy = T((y0 - kHalo + 0.5 * FHM - 0.5) * a.dy - gs.ay);
-                const T hx = T(0.5 * (kFW - 1)) * T(a.dx), hy = T(0.5 * (FHM - 1)) * T(a.dy);
-                const T hd = M<T>::sqrt(hx * hx + hy * hy);
-                const T sp = med3(cx * gs.exL + cy * gs.eyL, T(0), T(1));
-                const T qx = cx - sp * gs.ex, qy = cy - sp * gs.ey;
-                const T d = M<T>::sqrt(qx * qx + qy * qy);
-                const T mg = T(1) + T(1e-4) * (d + M<T>::sqrt(gs.ex * gs.ex + gs.ey * gs.ey));
-                geo_lb[tid] = d - hd - gs.rad - mg;
-                geo_ub[tid] = d + hd - gs.rad + mg;
-            }
+            if (on)
+                ign_frame_bounds(gs, x0 - kHalo, y0 - kHalo, FHM, a.dx, a.dy, geo_lb[tid],
+                                 geo_ub[tid]);
         }
         // the frame's largest psi^n (NaN nodes, which no ignition changes,
         // are ignored): an ignition whose psi_g is provably positive and no
@@ -271,7 +355,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
         T m = -INF;
 #pragma unroll
         for (int k = 0; k < KR; k++) m = vmax(m, p0[k]);
-        for (int off = 32; off > 0; off >>= 1) m = vmax(m, __shfl_xor(m, off));
+        m = wave_reduce_max(m);
         if ((tid & 63) == 0) wave_max[tid >> 6] = m;
         __syncthreads();
         for (int e = tid; e < a.nign * FHM; e += kBlock) {
@@ -546,7 +630,9 @@ template <typename T, int KR> constexpr int waves_per_simd() {
 // psi' (after ignition) and psi* (Heun stage 1) of every node and stops
 // there: ignition times, fuel fraction and fluxes are not recomputed.
 // mark (plain steps): where non-null, the step index a.mark_step is stored at
-// every node whose ignition time this step sets.
+// every node whose ignition time this step sets.  The ignition set-up of
+// the tiles comes from k_ign_plain (iuse, ilb, irow; read only while an
+// ignition is active).
 template <typename T, int KR, bool SMALL, bool REC>
 __global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
 k_step(const StepArgs a, const IgnTable<T> *itab, const T *__restrict__ psi_in,
@@ -554,14 +640,15 @@ k_step(const StepArgs a, const IgnTable<T> *itab, const T *__restrict__ psi_in,
        const T *__restrict__ vw, const T *__restrict__ dzdx, const T *__restrict__ dzdy,
        const uint8_t *__restrict__ cat, const T *__restrict__ coef, T *__restrict__ fsens,
        T *__restrict__ flat, int *status, T *__restrict__ rec_p0, T *__restrict__ rec_b,
-       int32_t *__restrict__ mark) {
+       int32_t *__restrict__ mark, const uint32_t *__restrict__ iuse, const T *__restrict__ ilb,
+       const T *__restrict__ irow) {
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * a.per_xcd + (bid >> 3);
     if (tile >= a.ntiles) return;
-    step_tile<T, KR, SMALL, REC>(a, tile, threadIdx.x, threadIdx.y, 0u, a.t, itab, psi_in,
-                                 psi_out, tign, frac, uw, vw,
-                                 dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b,
-                                 mark);
+    step_tile<T, KR, SMALL, REC, true>(a, tile, threadIdx.x, threadIdx.y, 0u, a.t, itab, psi_in,
+                                       psi_out, tign, frac, uw, vw,
+                                       dzdx, dzdy, cat, coef, fsens, flat, status, rec_p0, rec_b,
+                                       mark, iuse, ilb, irow);
 }
 
 // An ensemble of domains in one launch: the tiles of all domains form one
@@ -610,18 +697,19 @@ ens_tile(const StepArgs &common, const int g, const int tx, const int ty,
     if (SMALL) {
         // the member's first element goes into the 32-bit element index, so
         // the array bases stay the launch's (no per-member 64-bit pointers)
-        step_tile<T, KR, SMALL, false>(a, g - d.tile0, tx, ty, (uint32_t)d.cell_off, tnow, itab,
-                                       pin,
-                                       pout, tign, frac, uw, vw, dzdx, dzdy, cat, coef,
-                                       fsens + a0, flat + a0, status + di, nullptr, nullptr,
-                                       nullptr);
+        step_tile<T, KR, SMALL, false, false>(a, g - d.tile0, tx, ty, (uint32_t)d.cell_off,
+                                              tnow, itab, pin,
+                                              pout, tign, frac, uw, vw, dzdx, dzdy, cat, coef,
+                                              fsens + a0, flat + a0, status + di, nullptr,
+                                              nullptr, nullptr, nullptr, nullptr, nullptr);
     } else {
         const size_t c0 = (size_t)d.cell_off;
-        step_tile<T, KR, SMALL, false>(a, g - d.tile0, tx, ty, 0u, tnow, itab, pin + c0,
-                                       pout + c0,
-                                       tign + c0, frac + c0, uw + c0, vw + c0, dzdx + c0,
-                                       dzdy + c0, cat + c0, coef, fsens + a0, flat + a0,
-                                       status + di, nullptr, nullptr, nullptr);
+        step_tile<T, KR, SMALL, false, false>(a, g - d.tile0, tx, ty, 0u, tnow, itab, pin + c0,
+                                              pout + c0,
+                                              tign + c0, frac + c0, uw + c0, vw + c0, dzdx + c0,
+                                              dzdy + c0, cat + c0, coef, fsens + a0, flat + a0,
+                                              status + di, nullptr, nullptr, nullptr, nullptr,
+                                              nullptr, nullptr);
     }
 }
 
@@ -714,6 +802,72 @@ __global__ void k_ign_geo(const fire_ignition *__restrict__ ign, int nign, doubl
     IgnTable<T> *tab = reinterpret_cast<IgnTable<T> *>(tabs + (size_t)di * kIgnTableBytes);
     tab->g[g] = geo;
     tab->on[g] = on ? 1 : 0;
+}
+
+// A single domain's ignition set-up for the step at time t (IgnSetLayout),
+// ahead of the step kernel: every work-group forms the geometry of the
+// ignitions (work-group 0 also writes the table the step reads), then thread
+// i takes tile i (below the capacity) and table row i.  fhm: frame rows of
+// the step kernel (its bounds cover the whole frame).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_ign_plain(const fire_ignition *__restrict__ ign, int nign, double t, const StepArgs a,
+            int fhm, IgnTable<T> *__restrict__ tab, uint32_t *__restrict__ iuse,
+            T *__restrict__ ilb, T *__restrict__ irow) {
+    __shared__ IgnGeo<T> geo[FIRE_MAX_IGNITIONS];
+    __shared__ int on[FIRE_MAX_IGNITIONS];
+    const int tid = threadIdx.x;
+    if (tid < FIRE_MAX_IGNITIONS) {
+        IgnGeo<T> gm = {};
+        bool o = false;
+        if (tid < nign) o = ign_setup<T>(ign[tid], t, gm);
+        geo[tid] = gm;
+        on[tid] = o ? 1 : 0;
+        if (blockIdx.x == 0) {
+            tab->g[tid] = gm;
+            tab->on[tid] = o ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + tid;
+    const int ncap = a.ntiles < a.tile_cap ? a.ntiles : a.tile_cap;
+    if (i < ncap) {
+        const int tyi = i / a.tiles_x, txi = i - tyi * a.tiles_x;
+        const int fx0 = txi * a.tile_x - kHalo, fy0 = tyi * a.tile_y - kHalo;
+        T lb[FIRE_MAX_IGNITIONS], ub[FIRE_MAX_IGNITIONS];
+        for (int g = 0; g < nign; g++)
+            if (on[g]) ign_frame_bounds(geo[g], fx0, fy0, fhm, a.dx, a.dy, lb[g], ub[g]);
+        uint32_t word = 0;
+        for (int g = 0; g < nign; g++) {
+            if (!on[g]) continue;
+            int use = 2;
+            if (lb[g] > T(0)) {
+                // psi_g > 0 on every frame node: it lights no node there; and
+                // it is never the minimum where another active ignition's
+                // psi_g is below it everywhere
+                use = 1;
+                for (int h = 0; h < nign; h++)
+                    if (h != g && on[h] && ub[h] < lb[g]) use = 0;
+            }
+            word |= (uint32_t)use << (2 * g);
+            ilb[(size_t)i * FIRE_MAX_IGNITIONS + g] = lb[g];
+        }
+        iuse[i] = word;
+    }
+    if (i == 0) {   // tiles past the capacity: every active ignition in full
+        uint32_t word = 0;
+        for (int g = 0; g < nign; g++)
+            if (on[g]) word |= 2u << (2 * g);
+        iuse[a.tile_cap] = word;
+    }
+    if (i < a.ign_rows) {
+        for (int g = 0; g < nign; g++) {
+            if (!on[g]) continue;
+            const T py = ign_py(geo[g], i - kHalo, a.dy);
+            irow[(size_t)g * a.ign_rows + i] = py;
+            irow[(size_t)(FIRE_MAX_IGNITIONS + g) * a.ign_rows + i] = ign_by(geo[g], py);
+        }
+    }
 }
 
 // Advances an ensemble's device clock after its step kernel (stream order).
@@ -817,8 +971,20 @@ hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
     const int grid = a.per_xcd * 8;
     // the ignition geometry of the step: every step of an ensemble (its time
     // is on the device), a single domain's only while an ignition is active
-    if (b.ens_doms || a.nign > 0) {
-        const int nth = (b.ens_doms ? b.ndom : 1) * FIRE_MAX_IGNITIONS;
+    const char *iset = (const char *)b.ign_set;
+    const IgnSetLayout IL = ign_set_layout(a.tile_cap, a.ny, sizeof(T));
+    const uint32_t *iuse = iset ? (const uint32_t *)(iset + IL.use) : nullptr;
+    const T *ilb = iset ? (const T *)(iset + IL.lb) : nullptr;
+    const T *irow = iset ? (const T *)(iset + IL.rows) : nullptr;
+    if (!b.ens_doms && a.nign > 0) {
+        if (!iset || a.tile_cap < 0 || a.ign_rows < a.ny + kFHMax) return hipErrorInvalidValue;
+        const int nth = (a.ntiles < a.tile_cap ? a.ntiles : a.tile_cap) + 1;
+        const int n = nth > a.ign_rows ? nth : a.ign_rows;
+        hipLaunchKernelGGL((k_ign_plain<T>), dim3((n + 255) / 256), dim3(256), 0, s, b.ign,
+                           a.nign, a.t, a, kNR * KR, (IgnTable<T> *)b.ign_tab,
+                           (uint32_t *)iuse, (T *)ilb, (T *)irow);
+    } else if (b.ens_doms) {
+        const int nth = b.ndom * FIRE_MAX_IGNITIONS;
         hipLaunchKernelGGL((k_ign_geo<T>), dim3((nth + 63) / 64), dim3(64), 0, s, b.ign,
                            a.nign, a.t, b.ens_doms, b.ens_clock, b.ens_doms ? b.ndom : 1,
                            (char *)b.ign_tab, b.ens_slots > 0 ? b.ens_counters : nullptr);
@@ -843,14 +1009,14 @@ hipError_t launch_one(const StepArgs &a, const StepBuffers &b, hipStream_t s) {
                            (T *)b.tign, (T *)b.frac, (const T *)b.u, (const T *)b.v,
                            (const T *)b.dzdx, (const T *)b.dzdy, b.cat, (const T *)b.coef,
                            (T *)b.fsens, (T *)b.flat, b.status, (T *)b.rec_p0, (T *)b.rec_b,
-                           (int32_t *)nullptr);
+                           (int32_t *)nullptr, iuse, ilb, irow);
     } else {
         hipLaunchKernelGGL((k_step<T, KR, SMALL, false>), dim3(grid), dim3(kFW, kNR), dyn, s, a,
                            (const IgnTable<T> *)b.ign_tab, (const T *)b.psi_in, (T *)b.psi_out,
                            (T *)b.tign, (T *)b.frac, (const T *)b.u, (const T *)b.v,
                            (const T *)b.dzdx, (const T *)b.dzdy, b.cat, (const T *)b.coef,
                            (T *)b.fsens, (T *)b.flat, b.status, (T *)nullptr, (T *)nullptr,
-                           b.mark);
+                           b.mark, iuse, ilb, irow);
     }
     return hipGetLastError();
 }

@@ -57,9 +57,12 @@ def test_state_bytes_and_errors_without_gpu(lib):
     m = F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, F.FIRE_F32, 0)
     n = 128 * 96
     nb = lib.fire_state_bytes(C.byref(m), 13)
-    # psi x2, t_i, F (4 B each) plus the table, fuel staging, status word and
-    # the step's ignition geometry (at most 1 KiB)
-    assert 16 * n <= nb <= 16 * n + 8 * 256 + 13 * (10 * 4 + 112) + 256 + 1024
+    # psi x2, t_i, F (4 B each) plus the table, fuel staging, status word, the
+    # step's ignition geometry (at most 1 KiB) and its per-tile set-up: a word
+    # and 8 bounds for each of the 2 x 5 tiles of the default 120 x 20 tile,
+    # 16 row offsets for each of ny + 48 rows (three 256-byte aligned parts)
+    iset = 10 * (4 + 8 * 4) + 16 * (96 + 48) * 4
+    assert 16 * n + iset <= nb <= 16 * n + 8 * 256 + 13 * (10 * 4 + 112) + 256 + 1024 + iset + 3 * 256
     m64 = F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, F.FIRE_F64, 0)
     assert lib.fire_state_bytes(C.byref(m64), 13) >= 32 * n
     for bad in (F.fire_mesh(1, 96, 6.0, 6.0, 10, 10, 0, 0), F.fire_mesh(128, 96, 0.0, 6.0, 10, 10, 0, 0),

@@ -133,6 +133,56 @@ def test_ragged_and_tiny_meshes_fp64(shape, sr):
     run_fp64(prob, prob.steps)
 
 
+def _full_frame_problem(steps=60):
+    # refinement 11: a 121 x 22 tile fills its 28-row frame (22 + 2 x 3 halo
+    # rows = 4 x 7), so the ignition bounds must cover the last frame row too;
+    # four segments placed across tile rows and columns, their end points off
+    # the cell-centre lattice (a segment through a node centre at t = t_g
+    # makes psi_g = 0 there, with neighbours symmetric about it: the normal
+    # of Eq. (12) at that node is then decided by rounding)
+    nx, ny = 242, 264
+    rng = np.random.default_rng(1102)
+    fuels = synth.random_fuels(rng, 4)
+    cat = rng.integers(0, 4, (ny, nx)).astype(np.uint8)
+    gzx = rng.uniform(-0.1, 0.3, (ny, nx))
+    gzy = rng.uniform(-0.1, 0.3, (ny, nx))
+    u = rng.uniform(-1, 5, (ny, nx))
+    v = rng.uniform(-1, 5, (ny, nx))
+    d = 6.0
+    ign = [synth.ignition(60.13 * d, 20.37 * d, 100.41 * d, 24.93 * d, t_start=0.0, radius=9.0,
+                          ros=0.5),
+           synth.ignition(150.23 * d, 64.71 * d, 190.17 * d, 67.13 * d, t_start=1.0, radius=12.0,
+                          ros=0.5),
+           synth.ignition(40.37 * d, 130.61 * d, 41.73 * d, 160.29 * d, t_start=0.5, radius=8.0,
+                          ros=0.5),
+           synth.ignition(120.31 * d, 200.57 * d, 121.63 * d, 201.29 * d, t_start=2.0,
+                          radius=10.0, ros=0.5)]
+    return synth.Problem(nx, ny, d, d, 11, 11, fuels, cat, gzx, gzy, ign, 0.25, steps, [(u, v)],
+                         0, dict(viscosity=0.4, viscosity_mode=0, ros_cap=6.0,
+                                 boundary_policy=1, guard_width=1), name="fullframe")
+
+
+def test_full_frame_tiles_fp64():
+    run_fp64(_full_frame_problem(), 60, tile=(121, 22))
+
+
+def test_full_frame_tiles_bitwise_fp32():
+    prob = _full_frame_problem()
+    W = wind_tensors(prob, torch.float32)
+    outs = []
+    for tile in ((121, 22), (11, 11), (121, 11)):
+        g = gpu_fire(prob, torch.float32, tile=tile)
+        fs, fl = g.new_flux()
+        for _ in range(prob.steps):
+            g.step(W[0][0], W[0][1], prob.dt, fs, fl)
+        torch.cuda.synchronize()
+        outs.append((host(g.psi), host(g.tign), host(g.frac), host(fs), host(fl)))
+    assert np.isfinite(outs[0][1]).sum() > 100
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b, equal_nan=True)
+
+
 def test_drip_torch_and_literal_viscosity_fp64():
     prob = synth.patchy_fire(n=160, steps=100)
     c = 80 * 6.0

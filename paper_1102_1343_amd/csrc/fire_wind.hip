@@ -8,8 +8,9 @@
 //    share the face (the one column at the domain edge), and the value at
 //    z_f from the piecewise-linear interpolant in ln z through (ln z0, 0)
 //    and the level values above z0 (0 if z_f <= z0, the top value above the
-//    highest level).  Computed in double.
-// 2. k_wind_bilinear, one fire row per work-group: bilinear interpolation
+//    highest level).  Computed in double (float logarithms for float
+//    arrays, see ln_z).
+// 2. k_wind_bilinear, 8 fire rows per work-group: bilinear interpolation
 //    of each component from its staggered points, coordinates clamped to
 //    the points' extent, in the array precision -- first in y, once per
 //    point of the row's span (into LDS), then in x per fire cell.  The kernel
@@ -36,8 +37,20 @@ struct WindArgs {
     int32_t nax, nay, nz, sr_x, sr_y, nx, ny;
     int32_t vec;       // rows of 4k cells and 4-element-aligned outputs: vector stores
     double zf, g;
+    double lzf;        // ln z_f
     double rsx, rsy;   // 1 / sr_x, 1 / sr_y
 };
+
+// ln z of a height formed in double.  For a float result the logarithm is
+// taken in float (the hardware base-2 logarithm times ln 2: a few ulp,
+// ~1e-7 of the interpolation weights, far below the float rounding of the
+// result); heights stay in double, since they are differences of large
+// geopotential heights.  Double arrays take the double logarithm.
+template <typename T> __device__ __forceinline__ double ln_z(double z);
+template <> __device__ __forceinline__ double ln_z<float>(double z) {
+    return (double)(__builtin_amdgcn_logf((float)z) * 0.693147180559945309f);
+}
+template <> __device__ __forceinline__ double ln_z<double>(double z) { return ::log(z); }
 
 template <typename T>
 __device__ __forceinline__ double cell_z(const T *phi, const T *hgt, int ncol, int k, int c,
@@ -75,15 +88,15 @@ k_wind_vertical(const WindArgs a, const T *u3, const T *v3, const T *phi, const 
     const double zr = 0.5 * ((double)z0[ca] + (double)z0[cb]);
     double r = 0.0;
     if (a.zf > zr) {
-        const double lzf = ::log(a.zf);
-        double lz_prev = ::log(zr), v_prev = 0.0;
+        const double lzf = a.lzf;
+        double lz_prev = ln_z<T>(zr), v_prev = 0.0;
         bool done = false;
         for (int k = 0; k < a.nz && !done; k++) {
             const double zk = 0.5 * (cell_z(phi, hgt, ncol, k, ca, a.g) +
                                      cell_z(phi, hgt, ncol, k, cb, a.g));
             if (!(zk > zr)) continue;
             const double vk = (double)val[(size_t)k * np + pi];
-            const double lzk = ::log(zk);
+            const double lzk = ln_z<T>(zk);
             if (lzf <= lzk) {
                 r = v_prev + (lzf - lz_prev) * ((vk - v_prev) / (lzk - lz_prev));
                 done = true;
@@ -138,14 +151,17 @@ template <typename T> __device__ __forceinline__ Axis<T> axis(int N, int Dn, T r
     return r;
 }
 
-// One fire row per work-group, in chunks of kWChunk cells.  Per chunk the
-// y-interpolation is done once per staggered point the chunk spans, into a
-// line in LDS (the y weights are the same along the row); each thread then
-// interpolates 4 consecutive cells in x from that line and, when rows are
-// 4-aligned, stores them as one 16-byte non-temporal vector.  A fire centre is at
-// x/DX = (i + 1/2)/sr_x; u-points at (I, J + 1/2), v-points at (I + 1/2, J)
-// in atmosphere-cell units.  Arithmetic in the array precision.
+// A work-group takes kWChunk consecutive cells of kWRows consecutive fire
+// rows.  Per row the y-interpolation is done once per staggered point the
+// chunk spans, into a line in LDS (the y weights are the same along the row;
+// two lines alternate, so one barrier per row suffices); each thread then
+// interpolates its 4 consecutive cells in x from that line, with the x
+// positions and weights formed once for all the rows, and, when rows are
+// 4-aligned, stores them as one 16-byte non-temporal vector.  A fire centre
+// is at x/DX = (i + 1/2)/sr_x; u-points at (I, J + 1/2), v-points at
+// (I + 1/2, J) in atmosphere-cell units.  Arithmetic in the array precision.
 constexpr int kWChunk = 4 * kWB;
+constexpr int kWRows = 8;
 // staggered points a chunk can span: (kWChunk - 1)/sr_x + 3 at most
 constexpr int kWLine = kWChunk + 4;
 
@@ -154,40 +170,58 @@ template <typename T> using W4 = T __attribute__((ext_vector_type(4)));
 template <typename T>
 __global__ void __launch_bounds__(kWB)
 k_wind_bilinear(const WindArgs a, const T *uf, const T *vf, T *u, T *v) {
-    __shared__ T Lu[kWLine], Lv[kWLine];
-    const int j = blockIdx.x;
+    __shared__ T Lu[2][kWLine], Lv[2][kWLine];
+    // row bands along x (up to 2^21 of them), chunks along y (up to 2^14)
+    const int j0 = blockIdx.x * kWRows;
+    const int c0 = blockIdx.y * kWChunk;
     const int Dx = 2 * a.sr_x, Dy = 2 * a.sr_y;
     const T rx = T(a.rsx) * T(0.5), ry = T(a.rsy) * T(0.5);
-    // x/DX = (2i + 1) / (2 sr_x), shifted by -1/2 (= -sr_x / (2 sr_x)) for v
-    const Axis<T> uy = axis(2 * j + 1 - a.sr_y, Dy, ry, a.nay);
-    const Axis<T> vy = axis(2 * j + 1, Dy, ry, a.nay + 1);
-    const T *u0 = uf + (size_t)uy.k0 * (a.nax + 1), *u1 = uf + (size_t)uy.k1 * (a.nax + 1);
-    const T *v0 = vf + (size_t)vy.k0 * a.nax, *v1 = vf + (size_t)vy.k1 * a.nax;
-    const size_t row = (size_t)j * a.nx;
+    // x/DX = (2i + 1) / (2 sr_x), shifted by -1/2 (= -sr_x / (2 sr_x)) for v;
+    // point ranges [ub, ue], [vb, ve] of the chunk's cells
+    const int c1 = (c0 + kWChunk < a.nx ? c0 + kWChunk : a.nx) - 1;
+    const int ub = axis(2 * c0 + 1, Dx, rx, a.nax + 1).k0;
+    const int ue = axis(2 * c1 + 1, Dx, rx, a.nax + 1).k1;
+    const int vb = axis(2 * c0 + 1 - a.sr_x, Dx, rx, a.nax).k0;
+    const int ve = axis(2 * c1 + 1 - a.sr_x, Dx, rx, a.nax).k1;
+    // this thread's cells: line positions and weights, the same in every row
+    const int i0 = c0 + 4 * threadIdx.x;
+    int uk0[4], uk1[4], vk0[4], vk1[4];
+    T ut[4], vt[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int i = i0 + q < a.nx ? i0 + q : a.nx - 1;
+        const Axis<T> ux = axis(2 * i + 1, Dx, rx, a.nax + 1);
+        const Axis<T> vx = axis(2 * i + 1 - a.sr_x, Dx, rx, a.nax);
+        uk0[q] = ux.k0 - ub;
+        uk1[q] = ux.k1 - ub;
+        ut[q] = ux.t;
+        vk0[q] = vx.k0 - vb;
+        vk1[q] = vx.k1 - vb;
+        vt[q] = vx.t;
+    }
     const bool vec = a.vec != 0;
-    for (int c0 = 0; c0 < a.nx; c0 += kWChunk) {
-        const int c1 = (c0 + kWChunk < a.nx ? c0 + kWChunk : a.nx) - 1;
-        // point ranges [ub, ue], [vb, ve] of the chunk's cells
-        const int ub = axis(2 * c0 + 1, Dx, rx, a.nax + 1).k0;
-        const int ue = axis(2 * c1 + 1, Dx, rx, a.nax + 1).k1;
-        const int vb = axis(2 * c0 + 1 - a.sr_x, Dx, rx, a.nax).k0;
-        const int ve = axis(2 * c1 + 1 - a.sr_x, Dx, rx, a.nax).k1;
+    const int j1 = j0 + kWRows < a.ny ? j0 + kWRows : a.ny;
+    int p = 0;
+    for (int j = j0; j < j1; j++, p ^= 1) {
+        const Axis<T> uy = axis(2 * j + 1 - a.sr_y, Dy, ry, a.nay);
+        const Axis<T> vy = axis(2 * j + 1, Dy, ry, a.nay + 1);
+        const T *u0 = uf + (size_t)uy.k0 * (a.nax + 1), *u1 = uf + (size_t)uy.k1 * (a.nax + 1);
+        const T *v0 = vf + (size_t)vy.k0 * a.nax, *v1 = vf + (size_t)vy.k1 * a.nax;
+        // (line p was last read in row j - 2, before every thread reached the
+        // barrier of row j - 1)
         for (int q = threadIdx.x; q <= ue - ub && q < kWLine; q += kWB)
-            Lu[q] = (T(1) - uy.t) * u0[ub + q] + uy.t * u1[ub + q];
+            Lu[p][q] = (T(1) - uy.t) * u0[ub + q] + uy.t * u1[ub + q];
         for (int q = threadIdx.x; q <= ve - vb && q < kWLine; q += kWB)
-            Lv[q] = (T(1) - vy.t) * v0[vb + q] + vy.t * v1[vb + q];
+            Lv[p][q] = (T(1) - vy.t) * v0[vb + q] + vy.t * v1[vb + q];
         __syncthreads();
-        const int i0 = c0 + 4 * threadIdx.x;
         if (i0 < a.nx) {
             T ou[4], ov[4];
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int i = i0 + q < a.nx ? i0 + q : a.nx - 1;
-                const Axis<T> ux = axis(2 * i + 1, Dx, rx, a.nax + 1);
-                const Axis<T> vx = axis(2 * i + 1 - a.sr_x, Dx, rx, a.nax);
-                ou[q] = (T(1) - ux.t) * Lu[ux.k0 - ub] + ux.t * Lu[ux.k1 - ub];
-                ov[q] = (T(1) - vx.t) * Lv[vx.k0 - vb] + vx.t * Lv[vx.k1 - vb];
+                ou[q] = (T(1) - ut[q]) * Lu[p][uk0[q]] + ut[q] * Lu[p][uk1[q]];
+                ov[q] = (T(1) - vt[q]) * Lv[p][vk0[q]] + vt[q] * Lv[p][vk1[q]];
             }
+            const size_t row = (size_t)j * a.nx;
             if (vec) {   // streaming (non-temporal) stores: the output is not re-read here
                 const W4<T> wu = {ou[0], ou[1], ou[2], ou[3]}, wv = {ov[0], ov[1], ov[2], ov[3]};
                 __builtin_nontemporal_store(wu, reinterpret_cast<W4<T> *>(u + row + i0));
@@ -199,7 +233,6 @@ k_wind_bilinear(const WindArgs a, const T *uf, const T *vf, T *u, T *v) {
                 }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -237,6 +270,7 @@ hipError_t run(const fire_wind_grid *g, const void *u3, const void *v3, const vo
             ((uintptr_t)v % (4 * sizeof(T)) == 0);
     a.zf = g->zf;
     a.g = g->g;
+    a.lzf = std::log(g->zf);
     a.rsx = 1.0 / g->sr_x;   // 1/(2 sr) = rs / 2 is exact in binary
     a.rsy = 1.0 / g->sr_y;
     T *uf = (T *)scratch;
@@ -245,8 +279,9 @@ hipError_t run(const fire_wind_grid *g, const void *u3, const void *v3, const vo
     hipLaunchKernelGGL(k_wind_vertical<T>, dim3((npts + kWB - 1) / kWB), dim3(kWB), 0, s, a,
                        (const T *)u3, (const T *)v3, (const T *)phi, (const T *)hgt,
                        (const T *)z0, uf, vf);
-    hipLaunchKernelGGL(k_wind_bilinear<T>, dim3(g->ny), dim3(kWB), 0, s, a, (const T *)uf,
-                       (const T *)vf, (T *)u, (T *)v);
+    hipLaunchKernelGGL(k_wind_bilinear<T>,
+                       dim3((g->ny + kWRows - 1) / kWRows, (g->nx + kWChunk - 1) / kWChunk),
+                       dim3(kWB), 0, s, a, (const T *)uf, (const T *)vf, (T *)u, (T *)v);
     return hipGetLastError();
 }
 

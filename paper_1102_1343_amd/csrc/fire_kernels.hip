@@ -241,6 +241,12 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     // in-domain frame rows [ylo, yhi)
     const int ylo = kHalo - y0 > 0 ? kHalo - y0 : 0;
     const int yhi = ny - y0 + kHalo < FH ? ny - y0 + kHalo : FH;
+    // the in-domain rows of Heun stages 1 and 2 and of the fuel fraction:
+    // one range test per row and phase (no range masks shared between
+    // phases, which the compiler would keep for the whole kernel)
+    const int lo1 = max(1, ylo), hi1 = min(a.tile_y + 5, yhi);
+    const int lo2 = max(2, ylo), hi2 = min(a.tile_y + 4, yhi);
+    const int lo3 = max(3, ylo), hi3 = min(a.tile_y + 3, yhi);
     // a frame that lies inside the domain has no ghost nodes
     const bool interior = x0 >= kHalo && x0 + a.tile_x + kHalo <= nx && ylo == 0 && yhi == FH;
     // element index of frame row 0 (mod 2^32), plus the domain's first
@@ -432,7 +438,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     // unconditional loads need no register copies)
     auto in1 = [&](int k) {
         const int fy = ty + kNR * k;
-        return xr1 && fy >= 1 && fy < a.tile_y + 5 && fy >= ylo && fy < yhi;
+        return xr1 && fy >= lo1 && fy < hi1;
     };
     auto src1 = [&](int k) { return in1(k) ? idx0 + roff(k) : cbase; };
     Inputs<T> nxt = load_inputs<SMALL>(src1(0), cat, uw, vw, dzdx, dzdy);
@@ -465,7 +471,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     const int gw = a.guard;
     auto in2 = [&](int k) {
         const int fy = ty + kNR * k;
-        return xr2 && fy >= 2 && fy < a.tile_y + 4 && fy >= ylo && fy < yhi;
+        return xr2 && fy >= lo2 && fy < hi2;
     };
     auto src2 = [&](int k) { return in2(k) ? idx0 + roff(k) : cbase; };
     nxt = load_inputs<SMALL>(src2(0), cat, uw, vw, dzdx, dzdy);
@@ -535,7 +541,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     T fl[KR];
     auto in3 = [&](int k) {
         const int fy = ty + kNR * k;
-        return xr3 && fy >= 3 && fy < a.tile_y + 3 && fy >= ylo && fy < yhi;
+        return xr3 && fy >= lo3 && fy < hi3;
     };
     // F of row k + 1 is loaded while row k computes
     auto src3 = [&](int k) { return in3(k) ? idx0 + roff(k) : cbase; };

@@ -83,6 +83,15 @@ __device__ __forceinline__ void ghost_node(T (*P)[kFW], int fy, int fx, int gx, 
     }
 }
 
+// A copy of a wave-uniform value that the compiler cannot see through.  The
+// step takes one per phase for the frame-row bounds, so the per-row range
+// masks formed from them are not shared between phases (held across the
+// kernel, they would be spilled and reloaded row by row).
+__device__ __forceinline__ int phase_copy(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Lane permutations within each row of 16 lanes (DPP): swap neighbours,
 // swap pairs, mirror each half row, mirror the row.  A lane whose source is
 // unavailable keeps its own value.
@@ -145,15 +154,15 @@ __device__ __forceinline__ void ign_frame_bounds(const IgnGeo<T> &gs, int fx0, i
 // psi >= 0).  Four sub-cells with corners at the centre, two edge midpoints
 // and a cell corner, bilinear values, t^ reset to t' where psi >= 0 there.
 template <typename T>
-__device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW], int fy, int fx,
-                                           T tp, T rTf) {
+__device__ __forceinline__ T cell_fraction(const T (*A)[kFW], int fy, const T (*Q)[kFW], int qy,
+                                           int fx, T tp, T rTf) {
     T p[3][3], q[3][3];
 #pragma unroll
     for (int b = 0; b < 3; b++)
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             p[b][a] = A[fy + b - 1][fx + a - 1];
-            q[b][a] = Q[fy + b - 1][fx + a - 1];
+            q[b][a] = Q[qy + b - 1][fx + a - 1];
         }
     // edge midpoints and corners shared by neighbouring sub-cells
     const T pc = p[1][1], qc = q[1][1];
@@ -205,7 +214,11 @@ __device__ __forceinline__ T cell_fraction(const T (*A)[kFW], const T (*Q)[kFW],
 
 // The fused step.  KR = frame rows per thread (frame height <= 4 KR).
 // LDS frames: A holds psi^n, then psi^{n+1}, then the latent flux; B holds
-// psi*, then the sensible flux; C holds the node ignition times t^.
+// psi*, then the sensible flux; C holds the node ignition times t^.  Each
+// frame keeps only the rows it is used on: A all 4 KR, B frame rows
+// [1, 4 KR - 1) (row fy at B[fy - 1]), C rows [2, 4 KR - 2) (at C[fy - 2]).
+// At the default FP32 tile the plain step then needs under 40 KiB, so four
+// work-groups fit in a CU's 160 KiB.
 // PRE: the per-tile ignition set-up comes from iuse / ilb / irow (a single
 // domain's step); otherwise it is formed here from the geometry table.
 template <typename T, int KR, bool SMALL, bool REC, bool PRE>
@@ -220,8 +233,8 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
           const T *__restrict__ irow) {
     constexpr int FHM = kNR * KR;
     __shared__ T A[FHM][kFW];
-    __shared__ T B[FHM][kFW];
-    __shared__ T C[FHM][kFW];
+    __shared__ T B[FHM - 2][kFW];
+    __shared__ T C[FHM - 4][kFW];
     extern __shared__ __attribute__((aligned(32))) double dyn_smem[];
     T *tab = reinterpret_cast<T *>(dyn_smem);
     // the same table through an LDS pointer: 32-bit row addresses
@@ -264,7 +277,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     // multiply-add rebuilt from nx
     auto roff = [&](int k) {
         uint32_t r = (uint32_t)k * rstep;
-        asm("" : "+s"(r));
+        // asm("" : "+s"(r));
         return r;
     };
 
@@ -416,17 +429,21 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
         for (int k = 0; k < KR; k++)
             if (!(pold[k] > T(0) && p0[k] <= T(0))) tig[k] = INF;
     }
-#pragma unroll
-    for (int k = 0; k < KR; k++) {
-        const int fy = ty + kNR * k;
-        if (fy < FH) A[fy][tx] = p0[k];
-    }
-    __syncthreads();
-    if (!interior) {
+    {
+        const int fh = phase_copy(FH);
 #pragma unroll
         for (int k = 0; k < KR; k++) {
             const int fy = ty + kNR * k;
-            if (fy < FH) ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+            if (fy < fh) A[fy][tx] = p0[k];
+        }
+    }
+    __syncthreads();
+    if (!interior) {
+        const int fh = phase_copy(FH);
+#pragma unroll
+        for (int k = 0; k < KR; k++) {
+            const int fy = ty + kNR * k;
+            if (fy < fh) ghost_node(A, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
         }
         __syncthreads();
     }
@@ -450,15 +467,17 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
         if (in1(k)) {
             const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cur.cv, ncm1), (uint32_t)kLRow);
             const T F1 = rhs(A, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
-            B[fy][tx] = p0[k] + dt * F1;
+            B[fy - 1][tx] = p0[k] + dt * F1;
         }
     }
     __syncthreads();
     if (!interior) {
+        const int fhb = phase_copy(FH - 1);
 #pragma unroll
         for (int k = 0; k < KR; k++) {
             const int fy = ty + kNR * k;
-            if (fy < FH) ghost_node(B, fy, tx, gx, y0 - kHalo + fy, nx, ny, false);
+            if (fy >= 1 && fy < fhb)
+                ghost_node(B, fy - 1, tx, gx, y0 - kHalo + fy, nx, ny, false);
         }
         __syncthreads();
     }
@@ -484,9 +503,9 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
             const int gy = y0 - kHalo + fy;
             const uint32_t idx = idx0 + roff(k);
             const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cur.cv, ncm1), (uint32_t)kLRow);
-            const T F2 = rhs(B, fy, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
+            const T F2 = rhs(B, fy - 1, tx, cur.u, cur.v, cur.gx, cur.gy, row, c);
             const T pn0 = A[fy][tx];
-            const T pn = T(0.5) * (pn0 + B[fy][tx]) + hdt * F2;
+            const T pn = T(0.5) * (pn0 + B[fy - 1][tx]) + hdt * F2;
             A[fy][tx] = pn;   // stage-1 reads of A ended at the last barrier
             // t_i is read only where it can matter: a burning node, a node
             // crossing zero, or a node lit by this step's ignition
@@ -498,12 +517,12 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
                 if (pn0 > T(0) && pn <= T(0) && is_inf(ti))
                     ti = t + M<T>::div(pn0 * dt, pn0 - pn);
             }
-            if (!REC) C[fy][tx] = pn >= T(0) ? tp : ti;
+            if (!REC) C[fy - 2][tx] = pn >= T(0) ? tp : ti;
             if (xr3 && fy >= 3 && fy < a.tile_y + 3) {
                 at<SMALL>(psi_out, idx) = pn;
                 if (REC) {   // psi' and psi* of the step, for the reverse pass
                     at<SMALL>(rec_p0, idx) = pn0;
-                    at<SMALL>(rec_b, idx) = B[fy][tx];
+                    at<SMALL>(rec_b, idx) = B[fy - 1][tx];
                 } else {
                     if (!(ti == told)) {
                         at<SMALL>(tign, idx) = ti;
@@ -522,13 +541,15 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     __syncthreads();
     if (!interior) {
         // ghost psi re-extrapolated, corners included; ghost t^ = t' (R19)
+        const int fh = phase_copy(FH);
 #pragma unroll
         for (int k = 0; k < KR; k++) {
             const int fy = ty + kNR * k;
             const int gy = y0 - kHalo + fy;
-            if (fy < FH) {
+            if (fy < fh) {
                 ghost_node(A, fy, tx, gx, gy, nx, ny, true);
-                if (!(colin && gy >= 0 && gy < ny)) C[fy][tx] = tp;
+                if (!(colin && gy >= 0 && gy < ny) && fy >= 2 && fy < fh - 2)
+                    C[fy - 2][tx] = tp;
             }
         }
         __syncthreads();
@@ -564,7 +585,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
                 const int cv = at<SMALL>(cat, idx);
                 const lds_t<T> *row = tab3 + __umul24(min((uint32_t)cv, ncm1), (uint32_t)kLRow);
                 T Fn = T(1);
-                if (mn < T(0)) Fn = cell_fraction(A, C, fy, tx, tp, row[kLTf]);
+                if (mn < T(0)) Fn = cell_fraction(A, fy, C, fy - 2, tx, tp, row[kLTf]);
                 const T dF = (fo - Fn) * rdt;
                 fs = dF * row[kLCh];
                 fl[k] = dF * row[kLCq];
@@ -572,17 +593,21 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
                 if (!__builtin_isfinite(Fn)) st |= kStNonfinite;
             }
         }
-        if (fy < FH) B[fy][tx] = fs;
+        // (rows read by the reduction below)
+        if (fy >= kHalo && fy < a.tile_y + kHalo) B[fy - 1][tx] = fs;
     }
     if (st) atomicOr(status, st);
     __syncthreads();
 
     // ---- step 6: mean flux over each atmosphere cell of the tile, summed
     // in a fixed order (columns, then the column sums)
+    {
+        const int fh = phase_copy(FH);
 #pragma unroll
-    for (int k = 0; k < KR; k++) {
-        const int fy = ty + kNR * k;
-        if (fy < FH) A[fy][tx] = fl[k];
+        for (int k = 0; k < KR; k++) {
+            const int fy = ty + kNR * k;
+            if (fy < fh) A[fy][tx] = fl[k];
+        }
     }
     __syncthreads();
     const int nI = a.tile_x / a.sr_x, nJ = a.tile_y / a.sr_y;
@@ -591,10 +616,10 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
             const int r0 = kHalo + J * a.sr_y;
             T s1 = T(0), s2 = T(0);
             for (int r = 0; r < a.sr_y; r++) {
-                s1 += B[r0 + r][tx];
+                s1 += B[r0 + r - 1][tx];
                 s2 += A[r0 + r][tx];
             }
-            B[r0][tx] = s1;   // read above by this thread only
+            B[r0 - 1][tx] = s1;   // read above by this thread only
             A[r0][tx] = s2;
         }
     }
@@ -610,7 +635,7 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
         const int r0 = kHalo + J * a.sr_y, f0 = kHalo + I * a.sr_x;
         T s1 = T(0), s2 = T(0);
         for (int cI = 0; cI < a.sr_x; cI++) {
-            s1 += B[r0][f0 + cI];
+            s1 += B[r0 - 1][f0 + cI];
             s2 += A[r0][f0 + cI];
         }
         const T cnt = T(ncx * ncy);
@@ -631,6 +656,12 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
 template <typename T, int KR> constexpr int waves_per_simd() {
     return (sizeof(T) == 4 && KR == 7) ? 6 : 1;
 }
+// The plain step at that tile (no ignition scratch in LDS: its set-up comes
+// from k_ign_plain) needs under 40 KiB, so four work-groups fit per CU, i.e.
+// 8 waves per SIMD, within 64 VGPRs.
+template <typename T, int KR> constexpr int step_waves() {
+    return (sizeof(T) == 4 && KR == 7) ? 8 : waves_per_simd<T, KR>();
+}
 
 // REC: the replay of a recorded run for its reverse pass.  Writes psi^{n+1},
 // psi' (after ignition) and psi* (Heun stage 1) of every node and stops
@@ -640,7 +671,7 @@ template <typename T, int KR> constexpr int waves_per_simd() {
 // the tiles comes from k_ign_plain (iuse, ilb, irow; read only while an
 // ignition is active).
 template <typename T, int KR, bool SMALL, bool REC>
-__global__ void __launch_bounds__(kBlock, (waves_per_simd<T, KR>()))
+__global__ void __launch_bounds__(kBlock, (step_waves<T, KR>()))
 k_step(const StepArgs a, const IgnTable<T> *itab, const T *__restrict__ psi_in,
        T *__restrict__ psi_out, T *tign, T *frac, const T *__restrict__ uw,
        const T *__restrict__ vw, const T *__restrict__ dzdx, const T *__restrict__ dzdy,

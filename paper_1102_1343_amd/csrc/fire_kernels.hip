@@ -272,14 +272,10 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
     // the per-row multiply is uniform (scalar) work
     const uint32_t idx0 = off0 + (uint32_t)ty * unx;
     const uint32_t rstep = __builtin_amdgcn_readfirstlane((uint32_t)kNR * unx);
-    // k rstep held in a scalar register the compiler cannot see into (an
-    // empty asm): a full-rate vector add per row rather than a 64-bit
-    // multiply-add rebuilt from nx
-    auto roff = [&](int k) {
-        uint32_t r = (uint32_t)k * rstep;
-        // asm("" : "+s"(r));
-        return r;
-    };
+    // (k rstep is formed where it is used: held in scalar registers for the
+    // whole kernel, the seven offsets do not fit the scalar budget of four
+    // work-groups per CU)
+    auto roff = [&](int k) { return (uint32_t)k * rstep; };
 
     for (int i = tid; i < a.ncat; i += kBlock)
         make_row(coef + i * kNCoef, tab + i * kLRow, T(a.ros_cap));

@@ -644,17 +644,18 @@ step_tile(const StepArgs &a, const int tile, const int tx, const int ty, const u
 // One fire domain: work-group b takes tile (b % 8) * per_xcd + b / 8, so each
 // of the eight XCDs sweeps a contiguous band of row-major tiles and halo rows
 // stay in its L2.
-// Minimum waves per SIMD asked of the register allocator.  The FP32 frame of
-// the default 120 x 20 tile (KR = 7, 43 KiB of LDS) allows three work-groups
-// of 8 waves per CU, i.e. 6 waves per SIMD, which needs <= 80 VGPRs; the
-// ensemble kernel lands a few registers above that unless asked.  Elsewhere
-// the same request would force scratch spills, so nothing is asked (1).
+// Minimum waves per SIMD asked of the register allocator.  The ensemble
+// kernel at the default FP32 120 x 20 tile (KR = 7: 39 KiB of frames plus
+// its in-kernel ignition scratch) fits three work-groups of 8 waves per CU,
+// i.e. 6 waves per SIMD, which needs <= 80 VGPRs; it lands a few registers
+// above that unless asked.  Elsewhere the same request would force scratch
+// spills, so nothing is asked (1).
 template <typename T, int KR> constexpr int waves_per_simd() {
     return (sizeof(T) == 4 && KR == 7) ? 6 : 1;
 }
 // The plain step at that tile (no ignition scratch in LDS: its set-up comes
 // from k_ign_plain) needs under 40 KiB, so four work-groups fit per CU, i.e.
-// 8 waves per SIMD, within 64 VGPRs.
+// 8 waves per SIMD, within 64 VGPRs and the scalar registers of 8 waves.
 template <typename T, int KR> constexpr int step_waves() {
     return (sizeof(T) == 4 && KR == 7) ? 8 : waves_per_simd<T, KR>();
 }

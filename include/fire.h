@@ -160,7 +160,10 @@ int fire_init(fire_ctx **out, const fire_mesh *mesh, const fire_fuel *cats, int3
  * sensible and latent heat flux densities (W/m^2) over the step into
  * flux_sens / flux_lat (device atmosphere arrays) and updates the state in
  * the arena.  If out is not NULL it receives device pointers to the new
- * psi, t_i and F (valid until the next fire_step) and the new time.
+ * psi, t_i and F (valid until the next fire_step) and the new time.  Enqueues
+ * the fused step kernel and, while an ignition is active (Sect. 4.4), a small
+ * kernel before it that forms the step's ignition geometry and per-tile
+ * set-up in the arena.
  *
  * Boundary policy 0 (Sect. 4.1: the run terminates when fire reaches the
  * guard ring): after each step the status word is copied to pinned host
@@ -208,7 +211,11 @@ int fire_ros_eval(fire_ctx *ctx, const uint8_t *cat, const void *un, const void 
 
 /* Tile shape of the fused step kernel: tile_x a multiple of sr_x with
  * tile_x <= 122, tile_y a multiple of sr_y with tile_y <= 42 (FP32) or
- * <= 26 (FP64).  Results do not depend on the tile shape. */
+ * <= 26 (FP64).  Results do not depend on the tile shape.  The arena holds
+ * the per-tile ignition set-up for as many tiles as the default shape has;
+ * with a smaller tile the tiles past that count evaluate every active
+ * ignition at every node (same results, slower while ignitions are
+ * active). */
 int fire_set_tile(fire_ctx *ctx, int32_t tile_x, int32_t tile_y);
 int fire_get_tile(fire_ctx *ctx, int32_t *tile_x, int32_t *tile_y);
 

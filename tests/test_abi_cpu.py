@@ -64,7 +64,15 @@ def test_state_bytes_and_errors_without_gpu(lib):
     iset = 10 * (4 + 8 * 4) + 16 * (96 + 48) * 4
     assert 16 * n + iset <= nb <= 16 * n + 8 * 256 + 13 * (10 * 4 + 112) + 256 + 1024 + iset + 3 * 256
     m64 = F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, F.FIRE_F64, 0)
-    assert lib.fire_state_bytes(C.byref(m64), 13) >= 32 * n
+    iset64 = 10 * (4 + 8 * 8) + 16 * (96 + 48) * 8
+    nb64 = lib.fire_state_bytes(C.byref(m64), 13)
+    assert 32 * n + iset64 <= nb64 <= 32 * n + 8 * 256 + 13 * (10 * 8 + 112) + 256 + 1024 + iset64 + 3 * 256
+    # refinement 11: default tile 121 x 11, so 3 x 9 tiles of a 250 x 99 mesh
+    m11 = F.fire_mesh(250, 99, 6.0, 6.0, 11, 11, F.FIRE_F32, 0)
+    n11 = 250 * 99
+    iset11 = 27 * (4 + 8 * 4) + 16 * (99 + 48) * 4
+    nb11 = lib.fire_state_bytes(C.byref(m11), 13)
+    assert 16 * n11 + iset11 <= nb11 <= 16 * n11 + 8 * 256 + 13 * (10 * 4 + 112) + 256 + 1024 + iset11 + 3 * 256
     for bad in (F.fire_mesh(1, 96, 6.0, 6.0, 10, 10, 0, 0), F.fire_mesh(128, 96, 0.0, 6.0, 10, 10, 0, 0),
                 F.fire_mesh(128, 96, 6.0, 6.0, 0, 10, 0, 0), F.fire_mesh(128, 96, 6.0, 6.0, 10, 27, 0, 0),
                 F.fire_mesh(128, 96, 6.0, 6.0, 10, 10, 7, 0)):
